@@ -1,0 +1,169 @@
+"""Pins of the oracle's multigrid, smoothers and independent solvers (CPU only).
+
+* pure absorber (upwind, vacuum x-sides, zero-gradient y-sides): the discrete solution is the
+  closed-form recurrence psi_i = S/(4 pi s)(1 - r^(i+1)), r = 1/(1 + s h/mu), and converges at
+  first order to the continuum S/(4 pi s)(1 - exp(-s x/mu));
+* global balance of the converged upwind solution: h^2 sum(sigma_a phi - S) + leakage = 0;
+* nilpotency: N_x + N_y - 1 upwind Jacobi sweeps reproduce the exact transport sweep;
+* restriction / UpSamp identities: R(P(e)) = e and conservation of sum p h^2 rho;
+* the multigrid solve agrees with dense LU and with sweep-preconditioned GMRES, and the exact
+  solution is a fixed point of the sawtooth cycle;
+* infinite medium solved from zero reaches the closed form.
+"""
+import numpy as np
+import pytest
+
+from oracle import quadrature as qd
+from oracle.direct import dense_solve, gmres_solve, transport_sweep
+from oracle.multigrid import (PG, PG_FROZEN, UPWIND, Problem, finest_residual, rel_residual,
+                              restrict, sawtooth_cycle, solve, upsample, upwind_jacobi)
+from oracle.transport import VACUUM, ZERO_GRADIENT, pg_diffusivity, weighted_norm
+from workloads import WORKLOADS, make_inputs, scaled
+
+VAC = (VACUUM,) * 4
+ZG = (ZERO_GRADIENT,) * 4
+
+
+def _absorber(N, s=1.5, S=1.0, na=1):
+    st = np.full((1, N, N), s)
+    ss = np.zeros((1, 1, 1, N, N))
+    src = np.full((1, N, N), S)
+    return Problem(N, 1.0, 1, na, st, ss, src, bc=(VACUUM, VACUUM, ZERO_GRADIENT, ZERO_GRADIENT),
+                   disc=UPWIND)
+
+
+def test_pure_absorber_discrete_closed_form():
+    N, s, S = 16, 1.5, 1.0
+    prob = _absorber(N, s, S, na=2)
+    psi, hist, ok = solve(prob, rtol=1e-14, max_cycles=300)
+    assert ok
+    h = prob.h
+    for n in range(len(prob.quad["p"])):
+        mu = prob.quad["mu"][n]
+        r = 1.0 / (1.0 + s * h / abs(mu))
+        k = np.arange(N) if mu > 0 else np.arange(N)[::-1]
+        exact = S / (4 * np.pi * s) * (1 - r ** (k + 1))
+        assert np.allclose(psi[0, n], exact[None, :], rtol=1e-12, atol=0)
+
+
+def test_pure_absorber_first_order_convergence():
+    errs = []
+    s, S = 1.5, 1.0
+    for N in (32, 64, 128):
+        prob = _absorber(N, s, S)
+        x = transport_sweep(prob, np.broadcast_to(S / (4 * np.pi), prob.shape()).copy())
+        h = prob.h
+        xc = (np.arange(N) + 0.5) * h
+        n = 0
+        mu = prob.quad["mu"][n]
+        cont = S / (4 * np.pi * s) * (1 - np.exp(-s * (xc + 0.5 * h) / mu))
+        errs.append(np.abs(x[0, n, 0] - cont).max())
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all((orders > 0.85) & (orders < 1.15)), orders
+
+
+def _c0_small(N=16, na=2, disc=UPWIND, L=1.0, p=1, **kw):
+    w = scaled(WORKLOADS["c0_plain_fp64"], N)
+    st, ss, src = make_inputs(w)
+    return Problem(N, L, p, na, st, ss, src, disc=disc, **kw)
+
+
+def test_upwind_global_balance():
+    prob = _c0_small()
+    psi, hist, ok = solve(prob, rtol=1e-13, max_cycles=200)
+    assert ok
+    h, q = prob.h, prob.quad
+    phi = np.einsum("gnji,n->gji", psi, q["p"])
+    sig_a = prob.sigma_t - prob.sigma_s[0].sum(axis=0)
+    absorbed = h * h * np.sum(sig_a * phi - prob.source)
+    mu, nu, p = q["mu"], q["nu"], q["p"]
+    leak = 0.0
+    for n in range(len(p)):
+        col = psi[0, n, :, -1] if mu[n] > 0 else psi[0, n, :, 0]
+        row = psi[0, n, -1, :] if nu[n] > 0 else psi[0, n, 0, :]
+        leak += h * p[n] * (abs(mu[n]) * col.sum() + abs(nu[n]) * row.sum())
+    assert abs(absorbed + leak) < 1e-11 * h * h * np.sum(prob.source)
+
+
+def test_jacobi_nilpotent_without_scattering():
+    prob = _c0_small(N=8, na=1)
+    prob.sigma_s[:] = 0.0
+    rng = np.random.default_rng(0)
+    s = rng.normal(size=prob.shape())
+    e0 = rng.normal(size=prob.shape())
+    exact = transport_sweep(prob, s)
+    e = upwind_jacobi(prob, 0, e0, s, 8 + 8 - 1)
+    assert np.abs(e - exact).max() < 1e-12 * np.abs(exact).max()
+    e_short = upwind_jacobi(prob, 0, e0, s, 8 + 8 - 2)
+    assert np.abs(e_short - exact).max() > 1e-6
+
+
+def test_restriction_prolongation_identities():
+    prob = _c0_small(N=16, na=4)
+    rng = np.random.default_rng(1)
+    for l in range(len(prob.levels) - 1):
+        lf, lc = prob.levels[l], prob.levels[l + 1]
+        ec = rng.normal(size=prob.shape(l + 1))
+        assert np.allclose(restrict(upsample(ec, lf), lf, lc), ec, rtol=1e-14, atol=1e-14)
+        rho = rng.normal(size=prob.shape(l))
+        rc = restrict(rho, lf, lc)
+        fine = np.einsum("gnji,n->", rho, lf.quad["p"]) * lf.h ** 2
+        coarse = np.einsum("gnji,n->", rc, lc.quad["p"]) * lc.h ** 2
+        assert abs(fine - coarse) < 1e-12 * np.abs(rho).sum() * lf.h ** 2
+
+
+def test_level_hierarchy():
+    prob = _c0_small(N=32, na=4)
+    assert [(lv.N, lv.quad["na"]) for lv in prob.levels] == [(32, 4), (16, 2), (8, 1), (4, 1), (2, 1)]
+    odd = _c0_small(N=24, na=2)
+    assert [lv.N for lv in odd.levels] == [24, 12, 6, 3]
+
+
+def test_tiny_dense_lu_matches_gmres_and_multigrid():
+    prob = _c0_small(N=4, na=1)
+    x_lu = dense_solve(prob)
+    x_gm, rel = gmres_solve(prob, tol=1e-14)
+    assert rel < 1e-13
+    assert np.abs(x_lu - x_gm).max() < 1e-12 * np.abs(x_lu).max()
+    psi, hist, ok = solve(prob, rtol=1e-14, max_cycles=200)
+    assert ok and np.abs(psi - x_lu).max() < 1e-11 * np.abs(x_lu).max()
+
+
+def test_tiny_frozen_pg_dense_matches_gmres():
+    prob = _c0_small(N=6, na=1, disc=PG_FROZEN, p=2)
+    rng = np.random.default_rng(4)
+    prob.k_frozen = pg_diffusivity(rng.uniform(size=prob.shape()), prob.quad, prob.h, prob.h, 2, prob.bc)
+    x_lu = dense_solve(prob)
+    x_gm, rel = gmres_solve(prob, tol=1e-14)
+    assert rel < 1e-12
+    assert np.abs(x_lu - x_gm).max() < 1e-10 * np.abs(x_lu).max()
+    # rho(x_lu) = 0 for the frozen discretisation
+    assert rel_residual(prob, finest_residual(prob, x_lu)) < 1e-12
+
+
+def test_multigrid_solution_matches_gmres_and_is_a_fixed_point():
+    prob = _c0_small(N=16, na=2)
+    x_gm, rel = gmres_solve(prob, tol=1e-14)
+    psi, hist, ok = solve(prob, rtol=1e-13, max_cycles=200)
+    assert ok
+    assert weighted_norm(psi - x_gm, prob.quad, prob.h, prob.h) < 1e-11 * weighted_norm(x_gm, prob.quad, prob.h, prob.h)
+    nxt = sawtooth_cycle(prob, x_gm)
+    assert np.abs(nxt - x_gm).max() < 1e-11 * np.abs(x_gm).max()
+
+
+@pytest.mark.parametrize("disc,p", [(UPWIND, 1), (PG, 1), (PG, 2)])
+def test_infinite_medium_solve_reaches_closed_form(disc, p):
+    N, st, c, S = 8, 1.0, 0.5, 1.0
+    sigma_t = np.full((1, N, N), st)
+    prob = Problem(N, 8.0, p, 1, sigma_t, (c * sigma_t)[None, None], np.full((1, N, N), S),
+                   bc=ZG, disc=disc)
+    psi, hist, ok = solve(prob, rtol=1e-12, max_cycles=400)
+    assert ok
+    assert np.allclose(psi, S / (4 * np.pi * st * (1 - c)), rtol=1e-10)
+
+
+def test_pg_converges_on_optically_thick_cells():
+    # sigma_t h in [0.5, 2]: the sawtooth cycle with the non-linear PG reaches a tight residual
+    prob = _c0_small(N=16, na=2, disc=PG, L=16.0, p=2)
+    psi, hist, ok = solve(prob, rtol=1e-9, max_cycles=120)
+    assert ok, hist[-5:]

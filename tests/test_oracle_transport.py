@@ -1,0 +1,207 @@
+"""Pins of the oracle's transport operators against closed forms (CPU only).
+
+* infinite medium (zero-gradient halos everywhere, uniform data): psi = S / (4 pi sigma_a) makes
+  every residual vanish, for the upwind and the Petrov-Galerkin discretisations of every degree;
+  with downscatter the group fluxes follow by forward substitution;
+* manufactured solution: the truncation error of the PG residual falls with the formal order of
+  the ConvFEM stencils (2 / 4 / 4 for p = 1 / 2 / 3);
+* halo rule: incoming halo 0 and outgoing copy, checked node by node on a small grid;
+* the P1 emission leaves the particle balance unchanged (sum p mu = sum p nu = 0).
+"""
+import numpy as np
+import pytest
+
+from oracle import quadrature as qd
+from oracle.convfem import filters_2d
+from oracle.transport import (VACUUM, ZERO_GRADIENT, emission, halo_extend, moments,
+                              pg_diffusivity, pg_residual, upwind_residual, weighted_norm)
+
+ZG = (ZERO_GRADIENT,) * 4
+VAC = (VACUUM,) * 4
+
+
+def _uniform(G, N, val):
+    return np.full((G, N, N), float(val))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_infinite_medium_residual_vanishes(p):
+    N, na = 12, 2
+    quad = qd.quadrature(na)
+    st, c, S = 1.3, 0.7, 2.0
+    sigma_t = _uniform(1, N, st)
+    sigma_s = (c * sigma_t)[None, None]
+    source = _uniform(1, N, S)
+    psi = np.full((1, 8 * na * na, N, N), S / (4 * np.pi * (st - c * st)))
+    q = emission(psi, quad, sigma_s, source)
+    for r in (upwind_residual(psi, q, sigma_t, quad, 0.1, 0.1, ZG),
+              pg_residual(psi, q, sigma_t, quad, 0.1, 0.1, p, ZG)):
+        assert np.abs(r).max() < 1e-13 * np.abs(q).max()
+
+
+def test_infinite_medium_downscatter_closed_form():
+    # sigma_t0 phi0 = S0 + s00 phi0 ; sigma_t1 phi1 = s10 phi0 + s11 phi1 (forward substitution)
+    N, na = 8, 1
+    quad = qd.quadrature(na)
+    st0, st1, s00, s10, s11, S0 = 1.5, 0.8, 0.4, 0.5, 0.6, 1.0
+    phi0 = S0 / (st0 - s00)
+    phi1 = s10 * phi0 / (st1 - s11)
+    sigma_t = np.stack([_uniform(1, N, st0)[0], _uniform(1, N, st1)[0]])
+    sigma_s = np.zeros((1, 2, 2, N, N))
+    sigma_s[0, 0, 0], sigma_s[0, 1, 0], sigma_s[0, 1, 1] = s00, s10, s11
+    source = np.stack([_uniform(1, N, S0)[0], np.zeros((N, N))])
+    psi = np.zeros((2, 8, N, N))
+    psi[0], psi[1] = phi0 / (4 * np.pi), phi1 / (4 * np.pi)
+    q = emission(psi, quad, sigma_s, source)
+    for p in (1, 2):
+        r = pg_residual(psi, q, sigma_t, quad, 0.25, 0.25, p, ZG)
+        assert np.abs(r).max() < 1e-14
+
+
+def test_p1_emission_conserves_particles():
+    N, na = 6, 2
+    quad = qd.quadrature(na)
+    rng = np.random.default_rng(3)
+    psi = rng.uniform(size=(1, 32, N, N))
+    ss = np.zeros((2, 1, 1, N, N))
+    ss[0, 0, 0] = 0.5
+    ss1 = ss.copy()
+    ss1[1, 0, 0] = 0.3
+    q0 = emission(psi, quad, ss, np.zeros((1, N, N)))
+    q1 = emission(psi, quad, ss1, np.zeros((1, N, N)))
+    # the P1 part adds nothing to sum_n p_n q_n
+    assert np.allclose(np.einsum("gnji,n->gji", q1 - q0, quad["p"]), 0, atol=1e-15)
+    # and is 3/(4 pi) s1 (mu Phi1 + nu Phi2) for a purely linear angular flux psi = mu_n
+    lin = np.broadcast_to(quad["mu"][None, :, None, None], (1, 32, N, N)).copy()
+    Phi = moments(lin, quad)
+    assert np.allclose(Phi[0, 0], 0, atol=1e-14)
+    assert np.allclose(Phi[0, 1], np.dot(quad["p"], quad["mu"] ** 2))
+
+
+def test_halo_rule_vacuum_and_copy():
+    quad = qd.quadrature(1)
+    N = 4
+    psi = np.arange(1.0, 1 + 8 * N * N).reshape(1, 8, N, N)
+    ext = halo_extend(psi, quad["mu"], quad["nu"], 2, VAC)
+    for n in range(8):
+        mu, nu = quad["mu"][n], quad["nu"][n]
+        # x- side: zero when entering (mu > 0), else copy of column 0 on interior rows
+        left = ext[0, n, 2:2 + N, :2]
+        expect = 0 * left if mu > 0 else np.repeat(psi[0, n, :, :1], 2, axis=1)
+        assert np.array_equal(left, expect)
+        right = ext[0, n, 2:2 + N, 2 + N:]
+        expect = 0 * right if mu < 0 else np.repeat(psi[0, n, :, -1:], 2, axis=1)
+        assert np.array_equal(right, expect)
+        # corner: zero when entering through either side, else the corner node
+        corner = ext[0, n, 0, 0]
+        assert corner == (0.0 if (mu > 0 or nu > 0) else psi[0, n, 0, 0])
+        corner = ext[0, n, -1, -1]
+        assert corner == (0.0 if (mu < 0 or nu < 0) else psi[0, n, -1, -1])
+
+
+def test_upwind_residual_by_hand():
+    quad = qd.quadrature(1)
+    N, h = 3, 0.5
+    rng = np.random.default_rng(1)
+    psi = rng.normal(size=(1, 8, N, N))
+    st = rng.uniform(0.5, 2, size=(1, N, N))
+    q = rng.normal(size=(1, 8, N, N))
+    r = upwind_residual(psi, q, st, quad, h, h, VAC)
+    for n in range(8):
+        mu, nu = quad["mu"][n], quad["nu"][n]
+        for j in range(N):
+            for i in range(N):
+                def val(jj, ii):
+                    return psi[0, n, jj, ii] if (0 <= ii < N and 0 <= jj < N) else 0.0
+                if mu > 0:
+                    ax = mu * (val(j, i) - val(j, i - 1)) / h
+                else:
+                    ax = mu * (val(j, i + 1) - val(j, i)) / h
+                if nu > 0:
+                    ay = nu * (val(j, i) - val(j - 1, i)) / h
+                else:
+                    ay = nu * (val(j + 1, i) - val(j, i)) / h
+                ref = q[0, n, j, i] - ax - ay - st[0, j, i] * psi[0, n, j, i]
+                assert np.isclose(r[0, n, j, i], ref, rtol=1e-13, atol=1e-13)
+
+
+def _bump(x):
+    y = np.zeros_like(x)
+    t = (x - 0.2) / 0.6
+    m = (t > 0) & (t < 1)
+    y[m] = np.exp(-1.0 / (t[m] * (1 - t[m])) + 4.0)
+    return y
+
+
+def _dbump(x):
+    y = np.zeros_like(x)
+    t = (x - 0.2) / 0.6
+    m = (t > 0) & (t < 1)
+    tt = t[m]
+    y[m] = np.exp(-1.0 / (tt * (1 - tt)) + 4.0) * (1 - 2 * tt) / (tt * (1 - tt)) ** 2 / 0.6
+    return y
+
+
+def _mms_truncation(p, N, quad):
+    """||rho(psi_ms)||_W with the continuum source of a smooth compactly supported solution."""
+    h = 1.0 / N
+    xc = (np.arange(N) + 0.5) * h
+    X, Y = np.meshgrid(xc, xc, indexing="xy")
+    B, Bx, By = _bump(X) * _bump(Y), _dbump(X) * _bump(Y), _bump(X) * _dbump(Y)
+    mu, nu = quad["mu"], quad["nu"]
+    ang = 1 + 0.3 * mu + 0.2 * nu
+    psi = (B[None] * ang[:, None, None])[None]
+    sig = np.ones((1, N, N))
+    q = (psi * sig[:, None] + (mu * ang)[None, :, None, None] * Bx[None, None]
+         + (nu * ang)[None, :, None, None] * By[None, None])
+    r = pg_residual(psi, q, sig, quad, h, h, p, VAC)
+    return weighted_norm(r, quad, h, h)
+
+
+@pytest.mark.parametrize("p,order_lo,order_hi", [(1, 1.85, 2.15), (2, 3.6, 4.4), (3, 3.4, 4.4)])
+def test_manufactured_solution_truncation_order(p, order_lo, order_hi):
+    quad = qd.quadrature(1)
+    e1 = _mms_truncation(p, 64, quad)
+    e2 = _mms_truncation(p, 128, quad)
+    order = np.log2(e1 / e2)
+    assert order_lo < order < order_hi, order
+
+
+def test_pg_diffusivity_limits():
+    # k never exceeds k_max = dx |mu| and vanishes on a linear field (R = 0 there)
+    quad = qd.quadrature(2)
+    N, h = 10, 0.1
+    rng = np.random.default_rng(5)
+    psi = rng.uniform(size=(1, 32, N, N))
+    kx, ky = pg_diffusivity(psi, quad, h, h, 2, VAC)
+    assert np.all(kx <= h * np.abs(quad["mu"])[None, :, None, None] + 1e-15)
+    assert np.all(ky <= h * np.abs(quad["nu"])[None, :, None, None] + 1e-15)
+    assert np.all(kx >= 0) and np.all(ky >= 0)
+    N = 12
+    xc = (np.arange(N) + 0.5) * h
+    lin = np.broadcast_to((1 + xc)[None, None, None, :], (1, 32, N, N)).copy()
+    kx, ky = pg_diffusivity(lin, quad, h, h, 2, ZG)
+    # nodes at least 2p from the copied halo see an exactly linear field
+    assert np.abs(kx[..., 4:-4, 4:-4]).max() < 1e-12
+    assert np.abs(ky).max() < 1e-12
+
+
+def test_kdiff_symmetric_form():
+    # f(k psi; w) + k f(psi; w) - psi f(k; w) = sum_o w_o (k_c + k_o)(psi_o - psi_c), as sum w = 0
+    from oracle.transport import clamp_extend, k_diff
+    rng = np.random.default_rng(2)
+    p, n = 2, 5
+    w = filters_2d(p, 1.0, 1.0)["wDxx"]
+    assert abs(w.sum()) < 1e-14
+    ext = rng.normal(size=(1, 1, n + 2 * p, n + 2 * p))
+    k = rng.uniform(size=(1, 1, n, n))
+    kd = k_diff(ext, k, w, p)
+    kext = clamp_extend(k, p)
+    psi_c = ext[..., p:p + n, p:p + n]
+    ref = np.zeros_like(kd)
+    for v in range(-p, p + 1):
+        for u in range(-p, p + 1):
+            psi_o = ext[..., p + v:p + v + n, p + u:p + u + n]
+            k_o = kext[..., p + v:p + v + n, p + u:p + u + n]
+            ref += w[v + p, u + p] * (k + k_o) * (psi_o - psi_c)
+    assert np.allclose(kd, ref, atol=1e-12)
