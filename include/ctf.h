@@ -1,0 +1,194 @@
+/*
+ * ctf.h -- C-ABI of the MI355X (gfx950) ConvFEM space-angle multigrid transport library.
+ *
+ * Method: arXiv 2301.09991 (Phillips, Heaney, Chen, Buchan, Pain), "Solving the Discretised
+ * Boltzmann Transport Equations using Neural Networks".  The library solves the fixed-source,
+ * multigroup, discrete-ordinates transport equations (section "Boltzmann Transport Equation",
+ * fission term absent) on an N x N structured grid of the square [0, L]^2 with the octahedral
+ * 8 * na^2 ordinate set (section "Discrete Ordinates"), discretised either by first-order upwind
+ * control volumes (eq. discretised_hfm) or by ConvFEM filters of degree p with the anisotropic
+ * non-linear Petrov-Galerkin dissipation (eqs. Petrov, kxx, kyy, ano-k; Appendix A), and solved
+ * by the sawtooth space-angle multigrid cycle (section "Space-Angle Multigrid").
+ *
+ * Conventions shared by every call
+ *   - Angular-flux-shaped arrays are float64 [G][n_dir][N][N] (x fastest), with
+ *     n_dir = 8 * na^2 and ordinate index n = f * na^2 + a * na + b, f the octant face
+ *     (bit 0: mu < 0, bit 1: nu < 0, bit 2: xi < 0), a the patch row towards the pole and
+ *     b the patch column.  Offsets are 64-bit (N^2 * n_dir * G may exceed 2^31).
+ *   - rho = b - A(psi) is the residual, b_{g,n} = S_g / (4 pi).  A(psi) holds streaming,
+ *     Petrov-Galerkin dissipation, removal sigma_t psi and minus the scattering emission
+ *     (isotropic, plus linearly anisotropic when scatter_order = 1).
+ *   - Norms are ||v||_W = sqrt(sum p_n h^2 v^2); residuals are reported relative to ||b||_W.
+ *   - Every device pointer is owned by the caller; the library owns only the opaque host struct.
+ *     All device memory is carved from one caller-allocated workspace (ctf_workspace_bytes).
+ *   - Calls are asynchronous on the problem's HIP stream unless stated otherwise.  Calls on one
+ *     problem are not thread-safe; different problems on different streams are independent.
+ *   - Return codes: CTF_OK (0), CTF_NOT_CONVERGED (1) or a negative error; ctf_last_error()
+ *     returns a thread-local message describing the last failure.
+ */
+#ifndef CTF_H
+#define CTF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  CTF_OK = 0,
+  CTF_NOT_CONVERGED = 1,
+  CTF_EINVAL = -1,       /* bad configuration, shape or argument */
+  CTF_ENOMEM = -2,       /* workspace too small */
+  CTF_EHIP = -3,         /* a HIP runtime call failed */
+  CTF_ENONFINITE = -4,   /* NaN or Inf found in a residual norm */
+  CTF_EUNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+/* discretisation */
+enum { CTF_UPWIND = 0, CTF_CONVFEM_PG = 1, CTF_CONVFEM_PG_FROZEN_K = 2 };
+/* boundary condition per side (x-, x+, y-, y+) */
+enum { CTF_VACUUM = 0, CTF_ZERO_GRADIENT = 1 };
+/* arithmetic of the cycle; the outer residual and norms are always float64 */
+enum { CTF_FP64 = 0, CTF_FP32_IR = 1, CTF_FP32_IR_BF16_MOMENTS = 2 };
+/* apply_operator modes */
+enum { CTF_OP_APPLY = 0, CTF_OP_RESIDUAL = 1 };
+/* smoother kinds */
+enum { CTF_SMOOTH_UPWIND = 0, CTF_SMOOTH_FINEST = 1 };
+
+typedef struct ctf_config {
+  int n;               /* nodes per side of the finest grid (N x N), N >= 2 */
+  double length;       /* side L of the square domain; h = L / N */
+  int p;               /* ConvFEM degree 1..3 (ignored by CTF_UPWIND) */
+  int na;              /* ordinates per face side, a power of two: n_dir = 8 na^2 */
+  int ngroups;         /* G >= 1 */
+  int scatter_order;   /* 0 isotropic, 1 adds linearly anisotropic (P1) scattering */
+  int discretisation;  /* CTF_UPWIND, CTF_CONVFEM_PG, CTF_CONVFEM_PG_FROZEN_K */
+  int bc[4];           /* CTF_VACUUM or CTF_ZERO_GRADIENT for x-, x+, y-, y+ */
+  int precision;       /* CTF_FP64, CTF_FP32_IR, CTF_FP32_IR_BF16_MOMENTS */
+  int n_jacobi;        /* upwind Jacobi sweeps per level and cycle (>= 1) */
+  int n_pg;            /* finest-level smoothing sweeps after the update (>= 0) */
+  int max_levels;      /* 0: coarsen while N is even and > 2 */
+  double beta_pg;      /* Jacobi diagonal factor of the finest PG sweeps (paper: 3) */
+  double alpha_r;      /* factor of the anisotropic residual estimates (paper: 3) */
+  double eps_k;        /* epsilon_k of the diffusivities (paper: 0.001) */
+  int n_inner;         /* float32 cycles per float64 refinement step (precision != FP64) */
+} ctf_config;
+
+typedef struct ctf_problem ctf_problem;
+
+typedef struct ctf_level_desc {
+  int n;               /* nodes per side on this level */
+  int na;              /* ordinates per face side */
+  int n_dir;           /* 8 na^2 */
+  double h;            /* node spacing */
+  long long dof;       /* G * n_dir * n^2 */
+} ctf_level_desc;
+
+typedef struct ctf_solve_info {
+  int cycles;              /* sawtooth cycles performed */
+  int outer_steps;         /* float64 refinement steps (mixed precision) */
+  double rel_residual;     /* final ||rho||_W / ||b||_W, evaluated in float64 */
+  double seconds;          /* wall time of the call */
+  double* history;         /* optional caller buffer of history_len doubles: residual per check */
+  int history_len;
+} ctf_solve_info;
+
+/* Fill cfg with the paper's defaults: p = 1, na = 4, vacuum boundaries, upwind sweeps n_j = 2,
+ * n_pg = 2, beta_pg = 3, alpha_r = 3, eps_k = 1e-3, FP64, n_inner = 2. */
+void ctf_default_config(ctf_config* cfg);
+
+/* Bytes of device workspace a problem with this configuration needs (0 on invalid cfg; the
+ * reason is in ctf_last_error()). */
+size_t ctf_workspace_bytes(const ctf_config* cfg);
+
+/* Create a problem.
+ *   sigma_t  device float64 [G][N][N]             total cross-section (> 0 or = 0 for void)
+ *   sigma_s  device float64 [L_s+1][G][G][N][N]   scattering sigma_{s,l}(g_from -> g_to) stored
+ *                                                 [l][g_to][g_from]; L_s = scatter_order
+ *   source   device float64 [G][N][N]             isotropic external source S_g
+ *   workspace / ws_bytes: caller-owned device memory of at least ctf_workspace_bytes(cfg);
+ *   stream: the hipStream_t all work of this problem is queued on (NULL = default stream).
+ * The three inputs are copied into the workspace (they may be freed after return); the call
+ * builds the quadrature, the ConvFEM stencils and the level hierarchy (coarse sigma_t by the
+ * harmonic mean of 2x2 children) and synchronises the stream once.
+ * Errors: CTF_EINVAL (cfg), CTF_ENOMEM (workspace too small), CTF_EHIP. */
+int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const double* sigma_s,
+                       const double* source, void* workspace, size_t ws_bytes, void* stream,
+                       ctf_problem** out);
+
+/* Release the host-side problem (the workspace stays the caller's). NULL is ignored. */
+void ctf_destroy_problem(ctf_problem* prob);
+
+/* Number of multigrid levels, and one level's sizes. */
+int ctf_num_levels(const ctf_problem* prob);
+int ctf_level_info(const ctf_problem* prob, int level, ctf_level_desc* out);
+
+/* Host copies of one level's ordinates: mu, nu, w (weights p_n, summing to 4 pi), each n_dir
+ * doubles in caller-owned host memory (section "Discrete Ordinates"; coarse levels add the
+ * child patches: p summed, direction p-weighted). */
+int ctf_level_quadrature(const ctf_problem* prob, int level, double* mu, double* nu, double* w);
+
+/* The 1D ConvFEM stencils of degree p over offsets -p..p (2p+1 doubles each, host memory):
+ * normalised mass m, first derivative d (times 1/h) and negated second derivative k (times
+ * 1/h^2), from the averaged assembled rows of the degree-p element (section "ConvFEM",
+ * Appendix A: the 2D filters are their tensor products). */
+int ctf_convfem_stencils(int p, double* m, double* d, double* k);
+
+/* Host-only: the finest ordinates (mu, nu, w) of the 8 na^2 octahedral set, same as level 0 of
+ * ctf_level_quadrature; caller-owned host arrays of 8 na^2 doubles. */
+int ctf_quadrature(int na, double* mu, double* nu, double* w);
+
+/* Device copy of level `level`'s total cross-section, float64 [G][n][n] (caller buffer). */
+int ctf_level_sigma_t(const ctf_problem* prob, int level, double* out);
+
+/* A(psi) (mode CTF_OP_APPLY, no external source) or rho = b - A(psi) (CTF_OP_RESIDUAL) on the
+ * finest level (eq. Petrov, or eq. discretised_hfm for CTF_UPWIND).  psi and out: device
+ * float64 [G][n_dir][N][N], must not alias.  CTF_CONVFEM_PG_FROZEN_K uses the diffusivities held
+ * by the last ctf_freeze_k. */
+int ctf_apply_operator(ctf_problem* prob, const double* psi, double* out, int mode);
+
+/* Moments of psi: phi[g][m][j][i] = sum_n w_n Y_m(n) psi[g][n][j][i] with Y = (1, mu, nu)
+ * (section "Discrete Ordinates": phi_g = sum p_n psi_n).  phi: device float64 [G][3][N][N]. */
+int ctf_moments(ctf_problem* prob, const double* psi, double* phi);
+
+/* Compute and hold the PG diffusivities k_x, k_y of psi (eq. ano-k) for the frozen-k
+ * discretisation; if kx / ky are non-NULL they also receive a device float64 copy
+ * [G][n_dir][N][N]. */
+int ctf_freeze_k(ctf_problem* prob, const double* psi, double* kx, double* ky);
+
+/* nsweeps Jacobi sweeps (eq. matrix_full) in place on x.
+ *   CTF_SMOOTH_UPWIND: on level `level`, x <- x + (rhs - A_up x - sigma_t x)/d with the upwind
+ *     diagonal d = |mu|/h + |nu|/h + sigma_t (beta = 1); x, rhs sized for that level.
+ *   CTF_SMOOTH_FINEST: level 0 only, rhs must be NULL: psi <- psi + rho(psi)/(beta d) with the
+ *     finest discretisation's residual (beta = beta_pg for ConvFEM, 1 for upwind). */
+int ctf_smooth(ctf_problem* prob, int level, int kind, double* x, const double* rhs, int nsweeps);
+
+/* Restriction from level `level` to level+1 (section "Space-Angle Multigrid": weight by p_n h^2,
+ * sum the 2x2 cells and 2x2 child ordinates, divide by the coarse p_N H^2). */
+int ctf_restrict(ctf_problem* prob, int level, const double* fine, double* coarse);
+
+/* UpSamp from level+1 to level: every fine value copies its parent cell and ordinate. */
+int ctf_prolong(ctf_problem* prob, int level, const double* coarse, double* fine);
+
+/* One sawtooth cycle in place on psi (device float64 [G][n_dir][N][N]).  If rel_res is non-NULL
+ * the call synchronises and stores ||rho(psi_in)||_W / ||b||_W of the input psi. */
+int ctf_mg_cycle(ctf_problem* prob, double* psi, double* rel_res);
+
+/* Cycle until ||rho||_W / ||b||_W <= rtol (checked before every cycle) or max_cycles cycles;
+ * in place from the given psi (warm start).  With precision != CTF_FP64 every outer step
+ * evaluates rho in float64, runs n_inner float32 cycles on the correction equation (diffusivities
+ * frozen at the outer psi) and adds the correction in float64.  Synchronous.
+ * Returns CTF_OK, CTF_NOT_CONVERGED, or an error (CTF_ENONFINITE on a NaN/Inf residual). */
+int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_solve_info* info);
+
+/* ||v||_W of a finest-level array (synchronous). */
+int ctf_norm(ctf_problem* prob, const double* v, double* out);
+
+/* Thread-local description of the last error ("" if none). */
+const char* ctf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CTF_H */

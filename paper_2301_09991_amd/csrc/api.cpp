@@ -1,0 +1,739 @@
+// C-ABI of the solver (declared in include/ctf.h): problem setup, workspace layout and the
+// sawtooth-cycle / refinement drivers that queue the HIP kernels of kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ctf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define CTF_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(CTF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+int validate(const ctf_config* c) {
+  if (!c) return fail(CTF_EINVAL, "null config");
+  if (c->n < 2) return fail(CTF_EINVAL, "n must be >= 2");
+  if (!(c->length > 0.0)) return fail(CTF_EINVAL, "length must be > 0");
+  if (c->discretisation != CTF_UPWIND && (c->p < 1 || c->p > kMaxP))
+    return fail(CTF_EINVAL, "p must be 1..3");
+  if (!is_pow2(c->na)) return fail(CTF_EINVAL, "na must be a power of two");
+  if (c->ngroups < 1) return fail(CTF_EINVAL, "ngroups must be >= 1");
+  if (c->scatter_order < 0 || c->scatter_order > 1) return fail(CTF_EINVAL, "scatter_order 0 or 1");
+  if (c->discretisation < CTF_UPWIND || c->discretisation > CTF_CONVFEM_PG_FROZEN_K)
+    return fail(CTF_EINVAL, "bad discretisation");
+  for (int s = 0; s < 4; ++s)
+    if (c->bc[s] != CTF_VACUUM && c->bc[s] != CTF_ZERO_GRADIENT) return fail(CTF_EINVAL, "bad bc");
+  if (c->precision < CTF_FP64 || c->precision > CTF_FP32_IR_BF16_MOMENTS)
+    return fail(CTF_EINVAL, "bad precision");
+  if (c->n_jacobi < 1 || c->n_pg < 0) return fail(CTF_EINVAL, "n_jacobi >= 1 and n_pg >= 0");
+  if (c->max_levels < 0 || c->max_levels > kMaxLevels) return fail(CTF_EINVAL, "bad max_levels");
+  if (c->precision != CTF_FP64 && c->n_inner < 1) return fail(CTF_EINVAL, "n_inner >= 1");
+  if (!(c->beta_pg > 0.0) || !(c->eps_k > 0.0)) return fail(CTF_EINVAL, "beta_pg, eps_k > 0");
+  return CTF_OK;
+}
+
+int level_count(const ctf_config* c) {
+  int L = 1, n = c->n;
+  while (n % 2 == 0 && n > 2 && L < kMaxLevels && (c->max_levels == 0 || L < c->max_levels)) {
+    n /= 2;
+    ++L;
+  }
+  return L;
+}
+
+// bump allocator over the caller's workspace (256-byte aligned slices)
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+}  // namespace
+
+struct ctf_problem {
+  ctf_config cfg{};
+  hipStream_t stream = nullptr;
+  int L = 0;
+  int nmom = 1;  // moments the emission needs: 1 (isotropic) or 3 (P1)
+  LevelDims dims[kMaxLevels];
+  Quadrature quad[kMaxLevels];
+  // per level device data
+  double* dirs_d[kMaxLevels];  // mu | nu | w
+  float* dirs_f[kMaxLevels];
+  double* sigt_d[kMaxLevels];
+  float* sigt_f[kMaxLevels];
+  double* rho[kMaxLevels];
+  double* ea[kMaxLevels];
+  double* eb[kMaxLevels];
+  float* rho_f[kMaxLevels];
+  float* ea_f[kMaxLevels];
+  float* eb_f[kMaxLevels];
+  // finest-level data
+  double* sigma_s = nullptr;
+  double* source = nullptr;
+  float* sigma_s_f = nullptr;
+  double* phi = nullptr;
+  double* E = nullptr;
+  float* phi_f = nullptr;
+  float* E_f = nullptr;
+  double* psi_tmp = nullptr;
+  double* kx = nullptr;
+  double* ky = nullptr;
+  bool k_held = false;
+  float* kx_f = nullptr;
+  float* ky_f = nullptr;
+  float* e_f = nullptr;    // float32 correction of a refinement step
+  float* e_tmp_f = nullptr;
+  float* r_f = nullptr;    // float32 right-hand side of the correction equation
+  double* partial = nullptr;
+  double* scal = nullptr;  // device scalars
+  int npartial = 0;
+  double bnorm = 0.0;
+  Stencils<double> st_d{};
+  Stencils<float> st_f{};
+  PGParams pp{};
+  int bc_vac = 0;
+
+  size_t dof(int l) const { return size_t(dims[l].n) * dims[l].n * dims[l].nd * dims[l].G; }
+  LevelData<double> ld(int l) const {
+    const int nd = dims[l].nd;
+    return LevelData<double>{dims[l], dirs_d[l], dirs_d[l] + nd, dirs_d[l] + 2 * nd, sigt_d[l]};
+  }
+  LevelData<float> lf(int l) const {
+    const int nd = dims[l].nd;
+    return LevelData<float>{dims[l], dirs_f[l], dirs_f[l] + nd, dirs_f[l] + 2 * nd, sigt_f[l]};
+  }
+  bool mixed() const { return cfg.precision != CTF_FP64; }
+};
+
+namespace {
+
+// Lay out every device array of the problem over the workspace (base == nullptr: sizing pass).
+size_t layout(ctf_problem* P, char* base) {
+  Carver c{base};
+  const ctf_config& cfg = P->cfg;
+  const int G = cfg.ngroups;
+  const size_t nc0 = size_t(cfg.n) * cfg.n;
+  const bool mixed = cfg.precision != CTF_FP64;
+  for (int l = 0; l < P->L; ++l) {
+    const size_t dof = P->dof(l);
+    const size_t ncell = size_t(P->dims[l].n) * P->dims[l].n;
+    P->dirs_d[l] = c.take<double>(3 * size_t(P->dims[l].nd));
+    P->dirs_f[l] = c.take<float>(3 * size_t(P->dims[l].nd));
+    P->sigt_d[l] = c.take<double>(G * ncell);
+    P->sigt_f[l] = c.take<float>(G * ncell);
+    P->rho[l] = c.take<double>(dof);
+    P->ea[l] = c.take<double>(dof);
+    P->eb[l] = c.take<double>(dof);
+    if (mixed) {
+      P->rho_f[l] = c.take<float>(dof);
+      P->ea_f[l] = c.take<float>(dof);
+      P->eb_f[l] = c.take<float>(dof);
+    } else {
+      P->rho_f[l] = P->ea_f[l] = P->eb_f[l] = nullptr;
+    }
+  }
+  const int nl = cfg.scatter_order + 1;
+  P->sigma_s = c.take<double>(size_t(nl) * G * G * nc0);
+  P->source = c.take<double>(G * nc0);
+  P->phi = c.take<double>(3 * G * nc0);
+  P->E = c.take<double>(3 * G * nc0);
+  P->psi_tmp = c.take<double>(P->dof(0));
+  const bool need_k = cfg.discretisation != CTF_UPWIND;
+  P->kx = need_k ? c.take<double>(P->dof(0)) : nullptr;
+  P->ky = need_k ? c.take<double>(P->dof(0)) : nullptr;
+  if (mixed) {
+    P->sigma_s_f = c.take<float>(size_t(nl) * G * G * nc0);
+    P->phi_f = c.take<float>(3 * G * nc0);
+    P->E_f = c.take<float>(3 * G * nc0);
+    P->kx_f = need_k ? c.take<float>(P->dof(0)) : nullptr;
+    P->ky_f = need_k ? c.take<float>(P->dof(0)) : nullptr;
+    P->e_f = c.take<float>(P->dof(0));
+    P->e_tmp_f = c.take<float>(P->dof(0));
+    P->r_f = c.take<float>(P->dof(0));
+  }
+  P->npartial = wnorm2_partials(P->dims[0]);
+  P->partial = c.take<double>(P->npartial);
+  P->scal = c.take<double>(8);
+  return c.off + 256;
+}
+
+void init_dims(ctf_problem* P) {
+  const ctf_config& c = P->cfg;
+  P->L = level_count(&c);
+  int n = c.n, na = c.na;
+  double h = c.length / c.n;
+  for (int l = 0; l < P->L; ++l) {
+    P->dims[l] = LevelDims{n, 8 * na * na, na, c.ngroups, h};
+    n /= 2;
+    na = na > 1 ? na / 2 : 1;
+    h *= 2.0;
+  }
+}
+
+int check_level(const ctf_problem* P, int level) {
+  if (!P) return fail(CTF_EINVAL, "null problem");
+  if (level < 0 || level >= P->L) return fail(CTF_EINVAL, "level out of range");
+  return CTF_OK;
+}
+
+// ---- building blocks -------------------------------------------------------------------------
+// E <- emission of psi (source S if with_source, else none)
+int emission64(ctf_problem* P, const double* psi, bool with_source) {
+  const int nl = P->cfg.scatter_order + 1;
+  CTF_HIP(launch_moments<double>(P->ld(0), psi, P->phi, P->nmom, P->stream));
+  CTF_HIP(launch_emission<double>(P->dims[0], P->phi, P->sigma_s, nl,
+                                  with_source ? P->source : nullptr, P->E, P->stream));
+  return CTF_OK;
+}
+
+// out = sign * rho(psi) (mode 0) or out = psi + rho/(beta d) (mode 1), emission already in E
+int finest64(ctf_problem* P, const double* psi, double* out, int mode, double sign, double* kx_out,
+             double* ky_out) {
+  const ctf_config& c = P->cfg;
+  if (c.discretisation == CTF_UPWIND) {
+    CTF_HIP(launch_upwind_full<double>(P->ld(0), P->bc_vac, psi, P->E, P->nmom, out, mode, sign,
+                                       nullptr, P->stream));
+    return CTF_OK;
+  }
+  const bool frozen = c.discretisation == CTF_CONVFEM_PG_FROZEN_K;
+  if (frozen && !P->k_held) return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
+  CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, psi, P->E, P->nmom,
+                            frozen ? P->kx : nullptr, frozen ? P->ky : nullptr, out, kx_out, ky_out,
+                            mode, sign, nullptr, P->stream));
+  return CTF_OK;
+}
+
+int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
+  CTF_HIP(launch_wnorm2<double>(P->ld(level), v, P->partial, P->npartial, P->scal, P->stream));
+  double s2 = 0.0;
+  CTF_HIP(hipMemcpyAsync(&s2, P->scal, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  CTF_HIP(hipStreamSynchronize(P->stream));
+  *out_host = std::sqrt(s2);
+  if (!std::isfinite(*out_host)) return fail(CTF_ENONFINITE, "non-finite residual norm");
+  return CTF_OK;
+}
+
+// n upwind correction sweeps on level l: the first from (xmode, xsrc), result pointer returned;
+// acc != null: the last sweep adds into acc instead of writing a buffer.
+template <typename T>
+int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsrc, int xmode,
+                      const T* rhs, int nsweeps, T* bufa, T* bufb, T* acc, const T** result) {
+  const int nac = (l + 1 < P->L) ? P->dims[l + 1].na : 1;
+  const T* cur = xsrc;
+  int mode = xmode;
+  for (int s = 0; s < nsweeps; ++s) {
+    const bool last = s == nsweeps - 1;
+    T* dst = (s % 2 == 0) ? bufa : bufb;
+    CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, nac, rhs, dst,
+                                        (last && acc) ? acc : nullptr, P->stream));
+    cur = dst;
+    mode = 0;
+  }
+  if (result) *result = cur;
+  return CTF_OK;
+}
+
+// the part of the sawtooth cycle after rho_0 (in P->rho[0]) is known
+int cycle_rest64(ctf_problem* P, double* psi) {
+  const ctf_config& c = P->cfg;
+  const int L = P->L;
+  for (int l = 1; l < L; ++l)
+    CTF_HIP(launch_restrict<double>(P->ld(l - 1), P->ld(l), P->rho[l - 1], P->rho[l], P->stream));
+  const double* e = nullptr;
+  for (int l = L - 1; l >= 0; --l) {
+    const int xmode = (l == L - 1) ? 2 : 1;
+    int rc = correction_sweeps<double>(P, P->ld(l), l, e, xmode, P->rho[l], c.n_jacobi, P->ea[l],
+                                       P->eb[l], l == 0 ? psi : nullptr, &e);
+    if (rc) return rc;
+  }
+  // finest smoothing on the full equations
+  double* cur = psi;
+  double* other = P->psi_tmp;
+  for (int s = 0; s < c.n_pg; ++s) {
+    int rc = emission64(P, cur, true);
+    if (rc) return rc;
+    rc = finest64(P, cur, other, 1, 1.0, nullptr, nullptr);
+    if (rc) return rc;
+    std::swap(cur, other);
+  }
+  if (cur != psi)
+    CTF_HIP(hipMemcpyAsync(psi, cur, P->dof(0) * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+  return CTF_OK;
+}
+
+// ---- mixed precision: one float32 cycle on the correction equation A_k e = r --------------------
+// r (float32, P->r_f) is the float64 residual rounded; k is frozen at the outer psi; e in P->e_f.
+int inner_cycle32(ctf_problem* P, bool e_is_zero) {
+  const ctf_config& c = P->cfg;
+  const int L = P->L;
+  const int nl = c.scatter_order + 1;
+  // inner residual r - A e
+  if (e_is_zero) {
+    CTF_HIP(hipMemcpyAsync(P->rho_f[0], P->r_f, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice,
+                           P->stream));
+  } else {
+    CTF_HIP(launch_moments<float>(P->lf(0), P->e_f, P->phi_f, P->nmom, P->stream));
+    CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    if (c.discretisation == CTF_UPWIND) {
+      CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, P->e_f, P->E_f, P->nmom, P->rho_f[0], 0,
+                                        1.0f, P->r_f, P->stream));
+    } else {
+      CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, P->e_f, P->E_f, P->nmom, P->kx_f,
+                               P->ky_f, P->rho_f[0], nullptr, nullptr, 0, 1.0f, P->r_f, P->stream));
+    }
+  }
+  for (int l = 1; l < L; ++l)
+    CTF_HIP(launch_restrict<float>(P->lf(l - 1), P->lf(l), P->rho_f[l - 1], P->rho_f[l], P->stream));
+  const float* e = nullptr;
+  for (int l = L - 1; l >= 0; --l) {
+    const int xmode = (l == L - 1) ? 2 : 1;
+    if (l == 0 && e_is_zero) {
+      // e = 0 before this cycle: the correction sweeps' result is the new e itself
+      int rc = correction_sweeps<float>(P, P->lf(0), 0, e, xmode, P->rho_f[0], c.n_jacobi,
+                                        P->ea_f[0], P->eb_f[0], nullptr, &e);
+      if (rc) return rc;
+      CTF_HIP(hipMemcpyAsync(P->e_f, e, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+    } else {
+      int rc = correction_sweeps<float>(P, P->lf(l), l, e, xmode, P->rho_f[l], c.n_jacobi,
+                                        P->ea_f[l], P->eb_f[l], l == 0 ? P->e_f : nullptr, &e);
+      if (rc) return rc;
+    }
+  }
+  float* cur = P->e_f;
+  float* other = P->e_tmp_f;
+  for (int s = 0; s < c.n_pg; ++s) {
+    CTF_HIP(launch_moments<float>(P->lf(0), cur, P->phi_f, P->nmom, P->stream));
+    CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    if (c.discretisation == CTF_UPWIND) {
+      CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, cur, P->E_f, P->nmom, other, 1, 1.0f,
+                                        P->r_f, P->stream));
+    } else {
+      CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, cur, P->E_f, P->nmom, P->kx_f, P->ky_f,
+                               other, nullptr, nullptr, 1, 1.0f, P->r_f, P->stream));
+    }
+    std::swap(cur, other);
+  }
+  if (cur != P->e_f)
+    CTF_HIP(hipMemcpyAsync(P->e_f, cur, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+  return CTF_OK;
+}
+
+// float64 residual of psi into rho[0]; for ConvFEM also the diffusivities of psi (for the inner
+// float32 cycles).  Returns ||rho||_W / ||b||_W through rel.
+int outer_residual(ctf_problem* P, const double* psi, double* rel, bool keep_k) {
+  int rc = emission64(P, psi, true);
+  if (rc) return rc;
+  const bool pg = P->cfg.discretisation != CTF_UPWIND;
+  const bool frozen = P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K;
+  double* kxo = (pg && keep_k && !frozen) ? P->kx : nullptr;
+  double* kyo = (pg && keep_k && !frozen) ? P->ky : nullptr;
+  rc = finest64(P, psi, P->rho[0], 0, 1.0, kxo, kyo);
+  if (rc) return rc;
+  double nr = 0.0;
+  rc = wnorm64(P, 0, P->rho[0], &nr);
+  if (rc) return rc;
+  *rel = nr / P->bnorm;
+  return CTF_OK;
+}
+
+}  // namespace
+
+// ================================================================================================
+extern "C" {
+
+void ctf_default_config(ctf_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->n = 32;
+  c->length = 1.0;
+  c->p = 1;
+  c->na = 4;
+  c->ngroups = 1;
+  c->scatter_order = 0;
+  c->discretisation = CTF_CONVFEM_PG;
+  for (int s = 0; s < 4; ++s) c->bc[s] = CTF_VACUUM;
+  c->precision = CTF_FP64;
+  c->n_jacobi = 2;
+  c->n_pg = 2;
+  c->max_levels = 0;
+  c->beta_pg = 3.0;
+  c->alpha_r = 3.0;
+  c->eps_k = 1e-3;
+  c->n_inner = 2;
+}
+
+size_t ctf_workspace_bytes(const ctf_config* cfg) {
+  if (validate(cfg) != CTF_OK) return 0;
+  ctf_problem tmp;
+  tmp.cfg = *cfg;
+  init_dims(&tmp);
+  return layout(&tmp, nullptr);
+}
+
+int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const double* sigma_s,
+                       const double* source, void* workspace, size_t ws_bytes, void* stream,
+                       ctf_problem** out) {
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!out || !sigma_t || !sigma_s || !source || !workspace)
+    return fail(CTF_EINVAL, "null argument");
+  ctf_problem* P = new ctf_problem();
+  P->cfg = *cfg;
+  P->stream = static_cast<hipStream_t>(stream);
+  init_dims(P);
+  const size_t need = layout(P, nullptr);
+  if (ws_bytes < need) {
+    delete P;
+    return fail(CTF_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  // align the base to 256 bytes inside the caller's buffer
+  char* base = static_cast<char*>(workspace);
+  base += (256 - (reinterpret_cast<uintptr_t>(base) & 255)) & 255;
+  layout(P, base);
+  P->nmom = cfg->scatter_order ? 3 : 1;
+  P->bc_vac = 0;
+  for (int s = 0; s < 4; ++s)
+    if (cfg->bc[s] == CTF_VACUUM) P->bc_vac |= 1 << s;
+  const double h0 = cfg->length / cfg->n;
+  const int p = cfg->discretisation == CTF_UPWIND ? 1 : cfg->p;
+  {
+    double m[2 * kMaxP + 1], d[2 * kMaxP + 1], k[2 * kMaxP + 1];
+    convfem_stencils(p, m, d, k);
+    for (int i = 0; i < 2 * kMaxP + 1; ++i) {
+      const bool in = i < 2 * p + 1;
+      P->st_d.m[i] = in ? m[i] : 0.0;
+      P->st_d.d[i] = in ? d[i] / h0 : 0.0;
+      P->st_d.k[i] = in ? k[i] / (h0 * h0) : 0.0;
+      P->st_f.m[i] = float(P->st_d.m[i]);
+      P->st_f.d[i] = float(P->st_d.d[i]);
+      P->st_f.k[i] = float(P->st_d.k[i]);
+    }
+  }
+  P->pp.alpha_r = cfg->alpha_r;
+  P->pp.eps_k = cfg->eps_k;
+  P->pp.alpha_kabs = std::pow(2.0, p) / 16.0;
+  P->pp.alpha_ksq = std::pow(2.0, p) / 2.0;
+  P->pp.beta = cfg->beta_pg;
+  P->pp.bc_vac = P->bc_vac;
+
+  hipStream_t s = P->stream;
+  auto bail = [&](int code) {
+    delete P;
+    return code;
+  };
+  const int G = cfg->ngroups;
+  const size_t nc0 = size_t(cfg->n) * cfg->n;
+  const int nl = cfg->scatter_order + 1;
+  // quadrature per level
+  P->quad[0] = build_quadrature(cfg->na);
+  for (int l = 1; l < P->L; ++l) P->quad[l] = coarsen_quadrature(P->quad[l - 1]);
+  std::vector<std::vector<double>> hd(P->L);
+  std::vector<std::vector<float>> hf(P->L);
+  for (int l = 0; l < P->L; ++l) {
+    const int nd = P->dims[l].nd;
+    hd[l].resize(3 * nd);
+    hf[l].resize(3 * nd);
+    for (int n = 0; n < nd; ++n) {
+      hd[l][n] = P->quad[l].mu[n];
+      hd[l][nd + n] = P->quad[l].nu[n];
+      hd[l][2 * nd + n] = P->quad[l].w[n];
+    }
+    for (int i = 0; i < 3 * nd; ++i) hf[l][i] = float(hd[l][i]);
+    if (hipMemcpyAsync(P->dirs_d[l], hd[l].data(), 3 * nd * sizeof(double), hipMemcpyHostToDevice, s) ||
+        hipMemcpyAsync(P->dirs_f[l], hf[l].data(), 3 * nd * sizeof(float), hipMemcpyHostToDevice, s))
+      return bail(fail(CTF_EHIP, "copy of ordinates failed"));
+  }
+  if (hipMemcpyAsync(P->sigt_d[0], sigma_t, G * nc0 * sizeof(double), hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(P->sigma_s, sigma_s, nl * size_t(G) * G * nc0 * sizeof(double),
+                     hipMemcpyDeviceToDevice, s) ||
+      hipMemcpyAsync(P->source, source, G * nc0 * sizeof(double), hipMemcpyDeviceToDevice, s))
+    return bail(fail(CTF_EHIP, "copy of materials failed"));
+  for (int l = 1; l < P->L; ++l)
+    if (launch_harmonic_coarsen(P->sigt_d[l - 1], P->sigt_d[l], G, P->dims[l].n, s))
+      return bail(fail(CTF_EHIP, "harmonic coarsening failed"));
+  if (P->mixed()) {
+    for (int l = 0; l < P->L; ++l)
+      if (launch_convert_d2f(P->sigt_d[l], P->sigt_f[l], G * size_t(P->dims[l].n) * P->dims[l].n, s))
+        return bail(fail(CTF_EHIP, "conversion failed"));
+    if (launch_convert_d2f(P->sigma_s, P->sigma_s_f, nl * size_t(G) * G * nc0, s))
+      return bail(fail(CTF_EHIP, "conversion failed"));
+  }
+  // ||b||_W with b = S / (4 pi): sum_n w_n = 4 pi, so ||b||^2 = h^2 sum S^2 / (4 pi)
+  std::vector<double> src(G * nc0);
+  if (hipMemcpyAsync(src.data(), source, G * nc0 * sizeof(double), hipMemcpyDeviceToHost, s) ||
+      hipStreamSynchronize(s))
+    return bail(fail(CTF_EHIP, "source copy / sync failed"));
+  double ss = 0.0;
+  for (double v : src) ss += v * v;
+  P->bnorm = std::sqrt(ss * h0 * h0 / (4.0 * M_PI));
+  if (!(P->bnorm > 0.0)) P->bnorm = 1.0;  // no external source: report absolute norms
+  *out = P;
+  return CTF_OK;
+}
+
+void ctf_destroy_problem(ctf_problem* P) { delete P; }
+
+int ctf_num_levels(const ctf_problem* P) { return P ? P->L : 0; }
+
+int ctf_level_info(const ctf_problem* P, int level, ctf_level_desc* out) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  if (!out) return fail(CTF_EINVAL, "null out");
+  out->n = P->dims[level].n;
+  out->na = P->dims[level].na;
+  out->n_dir = P->dims[level].nd;
+  out->h = P->dims[level].h;
+  out->dof = static_cast<long long>(P->dof(level));
+  return CTF_OK;
+}
+
+int ctf_level_quadrature(const ctf_problem* P, int level, double* mu, double* nu, double* w) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  const Quadrature& q = P->quad[level];
+  const size_t nd = q.w.size();
+  if (mu) std::memcpy(mu, q.mu.data(), nd * sizeof(double));
+  if (nu) std::memcpy(nu, q.nu.data(), nd * sizeof(double));
+  if (w) std::memcpy(w, q.w.data(), nd * sizeof(double));
+  return CTF_OK;
+}
+
+int ctf_convfem_stencils(int p, double* m, double* d, double* k) {
+  if (p < 1 || p > kMaxP) return fail(CTF_EINVAL, "p must be 1..3");
+  double mm[2 * kMaxP + 1], dd[2 * kMaxP + 1], kk[2 * kMaxP + 1];
+  convfem_stencils(p, mm, dd, kk);
+  for (int i = 0; i < 2 * p + 1; ++i) {
+    if (m) m[i] = mm[i];
+    if (d) d[i] = dd[i];
+    if (k) k[i] = kk[i];
+  }
+  return CTF_OK;
+}
+
+int ctf_quadrature(int na, double* mu, double* nu, double* w) {
+  if (!is_pow2(na)) return fail(CTF_EINVAL, "na must be a power of two");
+  const Quadrature q = build_quadrature(na);
+  const size_t nd = q.w.size();
+  if (mu) std::memcpy(mu, q.mu.data(), nd * sizeof(double));
+  if (nu) std::memcpy(nu, q.nu.data(), nd * sizeof(double));
+  if (w) std::memcpy(w, q.w.data(), nd * sizeof(double));
+  return CTF_OK;
+}
+
+int ctf_level_sigma_t(const ctf_problem* P, int level, double* out) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  const size_t cnt = size_t(P->dims[level].G) * P->dims[level].n * P->dims[level].n;
+  CTF_HIP(hipMemcpyAsync(out, P->sigt_d[level], cnt * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+  return CTF_OK;
+}
+
+int ctf_apply_operator(ctf_problem* P, const double* psi, double* out, int mode) {
+  if (!P || !psi || !out) return fail(CTF_EINVAL, "null argument");
+  if (mode != CTF_OP_APPLY && mode != CTF_OP_RESIDUAL) return fail(CTF_EINVAL, "bad mode");
+  if (psi == out) return fail(CTF_EINVAL, "psi and out must not alias");
+  int rc = emission64(P, psi, mode == CTF_OP_RESIDUAL);
+  if (rc) return rc;
+  return finest64(P, psi, out, 0, mode == CTF_OP_RESIDUAL ? 1.0 : -1.0, nullptr, nullptr);
+}
+
+int ctf_moments(ctf_problem* P, const double* psi, double* phi) {
+  if (!P || !psi || !phi) return fail(CTF_EINVAL, "null argument");
+  CTF_HIP(launch_moments<double>(P->ld(0), psi, phi, 3, P->stream));
+  return CTF_OK;
+}
+
+int ctf_freeze_k(ctf_problem* P, const double* psi, double* kx, double* ky) {
+  if (!P || !psi) return fail(CTF_EINVAL, "null argument");
+  if (P->cfg.discretisation == CTF_UPWIND) return fail(CTF_EINVAL, "upwind has no diffusivities");
+  int rc = emission64(P, psi, true);
+  if (rc) return rc;
+  CTF_HIP(launch_pg<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, psi, P->E, P->nmom, nullptr, nullptr,
+                            P->psi_tmp, P->kx, P->ky, 0, 1.0, nullptr, P->stream));
+  P->k_held = true;
+  const size_t bytes = P->dof(0) * sizeof(double);
+  if (kx) CTF_HIP(hipMemcpyAsync(kx, P->kx, bytes, hipMemcpyDeviceToDevice, P->stream));
+  if (ky) CTF_HIP(hipMemcpyAsync(ky, P->ky, bytes, hipMemcpyDeviceToDevice, P->stream));
+  return CTF_OK;
+}
+
+int ctf_smooth(ctf_problem* P, int level, int kind, double* x, const double* rhs, int nsweeps) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  if (!x || nsweeps < 0) return fail(CTF_EINVAL, "bad argument");
+  if (kind == CTF_SMOOTH_UPWIND) {
+    if (!rhs) return fail(CTF_EINVAL, "upwind smoothing needs rhs");
+    if (nsweeps == 0) return CTF_OK;
+    const double* res = nullptr;
+    rc = correction_sweeps<double>(P, P->ld(level), level, x, 0, rhs, nsweeps, P->ea[level],
+                                   P->eb[level], nullptr, &res);
+    if (rc) return rc;
+    CTF_HIP(hipMemcpyAsync(x, res, P->dof(level) * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+    return CTF_OK;
+  }
+  if (kind == CTF_SMOOTH_FINEST) {
+    if (level != 0 || rhs) return fail(CTF_EINVAL, "finest smoothing: level 0 and rhs = NULL");
+    double* cur = x;
+    double* other = P->psi_tmp;
+    for (int s = 0; s < nsweeps; ++s) {
+      rc = emission64(P, cur, true);
+      if (rc) return rc;
+      rc = finest64(P, cur, other, 1, 1.0, nullptr, nullptr);
+      if (rc) return rc;
+      std::swap(cur, other);
+    }
+    if (cur != x)
+      CTF_HIP(hipMemcpyAsync(x, cur, P->dof(0) * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+    return CTF_OK;
+  }
+  return fail(CTF_EINVAL, "bad smoother kind");
+}
+
+int ctf_restrict(ctf_problem* P, int level, const double* fine, double* coarse) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  if (level + 1 >= P->L) return fail(CTF_EINVAL, "no coarser level");
+  CTF_HIP(launch_restrict<double>(P->ld(level), P->ld(level + 1), fine, coarse, P->stream));
+  return CTF_OK;
+}
+
+int ctf_prolong(ctf_problem* P, int level, const double* coarse, double* fine) {
+  int rc = check_level(P, level);
+  if (rc) return rc;
+  if (level + 1 >= P->L) return fail(CTF_EINVAL, "no coarser level");
+  CTF_HIP(launch_prolong<double>(P->ld(level), P->dims[level + 1].na, coarse, fine, P->stream));
+  return CTF_OK;
+}
+
+int ctf_norm(ctf_problem* P, const double* v, double* out) {
+  if (!P || !v || !out) return fail(CTF_EINVAL, "null argument");
+  return wnorm64(P, 0, v, out);
+}
+
+int ctf_mg_cycle(ctf_problem* P, double* psi, double* rel_res) {
+  if (!P || !psi) return fail(CTF_EINVAL, "null argument");
+  if (P->mixed()) {
+    // one refinement step: float64 residual, n_inner float32 cycles, float64 update
+    double rel = 0.0;
+    int rc = outer_residual(P, psi, &rel, true);
+    if (rc) return rc;
+    if (rel_res) *rel_res = rel;
+    const size_t n = P->dof(0);
+    CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
+    if (P->cfg.discretisation != CTF_UPWIND && P->cfg.discretisation != CTF_CONVFEM_PG_FROZEN_K) {
+      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
+      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
+    } else if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K) {
+      if (!P->k_held) return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
+      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
+      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
+    }
+    for (int it = 0; it < P->cfg.n_inner; ++it) {
+      rc = inner_cycle32(P, it == 0);
+      if (rc) return rc;
+    }
+    CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
+    return CTF_OK;
+  }
+  int rc = emission64(P, psi, true);
+  if (rc) return rc;
+  rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, nullptr);
+  if (rc) return rc;
+  if (rel_res) {
+    double nr = 0.0;
+    rc = wnorm64(P, 0, P->rho[0], &nr);
+    if (rc) return rc;
+    *rel_res = nr / P->bnorm;
+  }
+  return cycle_rest64(P, psi);
+}
+
+int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solve_info* info) {
+  if (!P || !psi || max_cycles < 0) return fail(CTF_EINVAL, "bad argument");
+  const auto t0 = std::chrono::steady_clock::now();
+  int cycles = 0, outer = 0, nhist = 0;
+  double rel = 0.0;
+  int status = CTF_NOT_CONVERGED;
+  for (;;) {
+    int rc;
+    if (P->mixed()) {
+      rc = outer_residual(P, psi, &rel, true);
+    } else {
+      rc = emission64(P, psi, true);
+      if (!rc) rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, nullptr);
+      if (!rc) {
+        double nr = 0.0;
+        rc = wnorm64(P, 0, P->rho[0], &nr);
+        rel = nr / P->bnorm;
+      }
+    }
+    if (rc) return rc;
+    if (info && info->history && nhist < info->history_len) info->history[nhist] = rel;
+    ++nhist;
+    if (rel <= rtol) {
+      status = CTF_OK;
+      break;
+    }
+    if (cycles >= max_cycles) break;
+    if (P->mixed()) {
+      const size_t n = P->dof(0);
+      CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
+      if (P->cfg.discretisation != CTF_UPWIND) {
+        if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !P->k_held)
+          return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
+        CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
+        CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
+      }
+      for (int it = 0; it < P->cfg.n_inner && cycles < max_cycles; ++it, ++cycles) {
+        rc = inner_cycle32(P, it == 0);
+        if (rc) return rc;
+      }
+      CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
+      ++outer;
+    } else {
+      rc = cycle_rest64(P, psi);
+      if (rc) return rc;
+      ++cycles;
+    }
+  }
+  CTF_HIP(hipStreamSynchronize(P->stream));
+  if (info) {
+    info->cycles = cycles;
+    info->outer_steps = outer;
+    info->rel_residual = rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  }
+  return status;
+}
+
+const char* ctf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Internal declarations shared by the host driver (api.cpp, setup.cpp) and the HIP kernels
+// (kernels.hip).  Nothing here crosses the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/ctf.h"
+
+namespace ctf {
+
+constexpr int kMaxP = 3;
+constexpr int kMaxLevels = 16;
+
+// ---- host-side setup (setup.cpp) ---------------------------------------------------------------
+struct Quadrature {
+  int na = 0;
+  std::vector<double> mu, nu, xi, w;  // n_dir each, w sums to 4 pi
+};
+
+// Finest ordinates of the octahedral patch set (section "Discrete Ordinates").
+Quadrature build_quadrature(int na);
+// Coarse ordinates: children patches added (section "Space-Angle Multigrid").
+Quadrature coarsen_quadrature(const Quadrature& q);
+// Parent ordinate of fine ordinate n on a face grid of na x na (identity once na == 1).
+inline int parent_dir(int n, int na) {
+  if (na == 1) return n;
+  int f = n / (na * na), r = n % (na * na);
+  int a = r / na, b = r % na, nc = na / 2;
+  return f * nc * nc + (a / 2) * nc + (b / 2);
+}
+// 1D ConvFEM stencils (m, d, k), 2p+1 entries each (Appendix A construction).
+void convfem_stencils(int p, double* m, double* d, double* k);
+
+// ---- device kernel arguments -------------------------------------------------------------------
+// Stencils are passed by value (tiny) so that every kernel reads them from its argument segment.
+template <typename T>
+struct Stencils {
+  T m[2 * kMaxP + 1];
+  T d[2 * kMaxP + 1];  // already divided by h
+  T k[2 * kMaxP + 1];  // already divided by h^2
+};
+
+struct LevelDims {
+  int n;        // nodes per side
+  int nd;       // ordinates
+  int na;
+  int G;
+  double h;
+};
+
+template <typename T>
+struct LevelData {
+  LevelDims dims;
+  const T* mu;       // [nd]
+  const T* nu;       // [nd]
+  const T* w;        // [nd]
+  const T* sigma_t;  // [G][n][n]
+};
+
+// bc bits: bit s set <=> side s (x-, x+, y-, y+) is vacuum
+struct PGParams {
+  double alpha_r, eps_k, alpha_kabs, alpha_ksq, beta;
+  int bc_vac;
+};
+
+// ---- kernel launchers (kernels.hip) ------------------------------------------------------------
+// Every launcher queues work on `s` and returns hipGetLastError().
+template <typename T>
+hipError_t launch_moments(const LevelData<T>& L, const T* psi, T* phi, int nmom, hipStream_t s);
+
+// E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2 (E1, E2 only if nl == 2), divided by 4 pi;
+// source == null: no external source.
+template <typename T>
+hipError_t launch_emission(const LevelDims& d, const T* phi, const T* sigma_s, int nl,
+                           const T* source, T* E, hipStream_t s);
+
+// Finest ConvFEM Petrov-Galerkin operator.
+//   mode 0: out = sign * rho;   mode 1: out = psi + rho / (beta d)
+//   kx, ky != null: frozen diffusivities (else computed from psi)
+//   kx_out, ky_out != null: store the diffusivities computed from psi (mode 0 only)
+//   rhs != null: a per-DOF term added to the emission (right-hand side of a correction equation)
+template <typename T>
+hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
+                     const T* psi, const T* E, int nmomE, const T* kx, const T* ky, T* out,
+                     T* kx_out, T* ky_out, int mode, T sign, const T* rhs, hipStream_t s);
+
+// Finest upwind operator: mode 0 out = sign * rho, mode 1 out = psi + rho / d.
+template <typename T>
+hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, const T* E,
+                              int nmomE, T* out, int mode, T sign, const T* rhs, hipStream_t s);
+
+// Correction sweep e_new = e + (rhs - A_up e - sigma_t e) / d on one level.
+//   xmode 0: e from x_in;  1: e = UpSamp(x_coarse) (x_in is the level+1 array, nac its na);
+//   2: e = 0.   psi_acc != null: psi_acc += e_new instead of writing x_out.
+template <typename T>
+hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
+                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s);
+
+template <typename T>
+hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine,
+                           T* coarse, hipStream_t s);
+
+template <typename T>
+hipError_t launch_prolong(const LevelData<T>& Lf, int nac, const T* coarse, T* fine, hipStream_t s);
+
+// partial[b] = sum over block b of w_n h^2 v^2, then out[0] = sum of partials (fixed order).
+template <typename T>
+hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int npartial,
+                         double* out, hipStream_t s);
+int wnorm2_partials(const LevelDims& d);
+
+template <typename T>
+hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s);
+
+hipError_t launch_harmonic_coarsen(const double* fine, double* coarse, int G, int nc, hipStream_t s);
+
+// precision conversions
+hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s);
+// y(double) += x(float)
+hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s);
+
+}  // namespace ctf

@@ -1,0 +1,71 @@
+"""The C-ABI library: it loads, exports every symbol include/ctf.h declares, and its host-only
+setup (ordinates, ConvFEM stencils, configuration checks) agrees with the oracle.  CPU only: no
+call here touches a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2301_09991_amd import ctf
+from oracle import convfem, quadrature as qd
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ctf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ctf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(ctf.LIB_PATH)
+    names = _declared()
+    assert len(names) >= 20
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(ctf.EXPORTED) == names
+
+
+@pytest.mark.parametrize("na", [1, 2, 4, 8, 16])
+def test_host_quadrature_matches_oracle(na):
+    mu, nu, w = ctf.quadrature(na)
+    q = qd.quadrature(na)
+    assert np.abs(mu - q["mu"]).max() < 1e-13
+    assert np.abs(nu - q["nu"]).max() < 1e-13
+    assert np.abs(w - q["p"]).max() < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_host_stencils_match_oracle(p):
+    m, d, k = ctf.convfem_stencils(p)
+    mo, do, ko = convfem.stencils_1d_float(p)
+    assert np.abs(m - mo).max() < 1e-14
+    assert np.abs(d - do).max() < 1e-14
+    assert np.abs(k - ko).max() < 1e-13
+
+
+def test_config_validation():
+    with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(na=3))
+    with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(p=4))
+    with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(n=1))
+    with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(n_jacobi=0))
+    with pytest.raises(ctf.CtfError):
+        ctf.convfem_stencils(0)
+    small = ctf.workspace_bytes(ctf.default_config(n=32))
+    big = ctf.workspace_bytes(ctf.default_config(n=64))
+    assert 3.5 * small < big < 4.5 * small
+    mixed = ctf.workspace_bytes(ctf.default_config(n=64, precision=ctf.FP32_IR))
+    assert mixed > big
+
+
+def test_default_config_is_the_papers():
+    c = ctf.default_config()
+    assert c.beta_pg == 3.0 and c.alpha_r == 3.0 and c.eps_k == 1e-3
+    assert c.n_jacobi == 2 and c.bc[:] == [ctf.VACUUM] * 4
