@@ -1,0 +1,174 @@
+"""Throughput benchmark of the ConvFEM space-angle multigrid solver on one MI355X.
+
+Workload (the mixed-precision workload): 256 x 256 nodes on the unit square, biquadratic ConvFEM
+(p = 2) with the non-linear anisotropic Petrov-Galerkin dissipation, 512 ordinates (octahedral,
+8 x 8 patches per face = 16 polar x 32 azimuthal), 2 energy groups with downscatter-only
+scattering, coefficients piecewise constant on 16 x 16-cell patches, Gaussian source (sigma 0.1).
+All inputs are seeded synthetic arrays (workloads.make_inputs).
+
+One step = one refinement step of the solver: float64 residual (with the diffusivities of the
+current psi) + float64 norm, n_inner = 2 float32 sawtooth cycles on the correction equation, and
+the float64 update.  value = finest DOF x float32 cycles / second.  Inputs are resident in HBM
+before the timed region starts.
+
+Prints ONE JSON line (see the repository's measurement notes for the roofline fields).
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "space-angle DOF-updates/s; time-to-1e-6 residual, learned+mixed vs plain FP64 MG"
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_TFLOPS = 157.3
+FP64_VALU_TFLOPS = 78.6
+
+
+def algorithmic_cost(kernel, p, nmom=1):
+    """Algorithmic bytes and flops per finest DOF of one launch of a kernel class.
+
+    Bytes: arrays every DOF must read / write once (per-cell data shared by all ordinates is
+    amortised to ~0).  Flops: 2 x multiply-adds of the separable (tensor-product) evaluation.
+    """
+    taps = 2 * p + 1
+    grad = 2 * (2 * taps - 1)                # Psi_x, Psi_y: x-pass (d, m) then y-pass (m, d)
+    kdiff = 2 * 3 * 2 * taps                 # f(k psi; w) + k f(psi; w) - psi f(k; w), x and y
+    resid_est = 2 * 2 * taps                 # R_x, R_y: m (x) m on Psi_x, Psi_y
+    if kernel == "pg32":                     # frozen k, rhs: read e, kx, ky, r; write e_new
+        return 4 * 5, 2 * (grad + kdiff) + 12
+    if kernel == "pg64":                     # k from psi; read psi, write rho, write kx, ky
+        return 8 * 4, 2 * (grad + kdiff + resid_est) + 40
+    if kernel in ("corr0", "upwind64", "upwind32"):
+        b = 4 if kernel != "upwind64" else 8
+        return 3 * b, 12
+    raise KeyError(kernel)
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """Time the FP64 oracle (single thread) on a bounded sample: one sawtooth cycle of the same
+    workload recipe at N = 64 (same p, ordinates, groups), in a subprocess."""
+    code = r"""
+import json, os, sys, time
+sys.path.insert(0, %r)
+from oracle import multigrid as omg
+from workloads import WORKLOADS, make_inputs, scaled
+w = scaled(WORKLOADS["c1_mixed"], 64)
+st, ss, src = make_inputs(w)
+prob = omg.Problem(w.N, w.L, w.p, w.na, st, ss, src, disc=omg.PG)
+import numpy as np
+psi = np.zeros(prob.shape())
+t = time.time(); cycles = 0
+while True:
+    psi = omg.sawtooth_cycle(prob, psi); cycles += 1
+    if time.time() - t > %f or cycles >= 3:
+        break
+dt = time.time() - t
+print(json.dumps({"dof": w.dof, "cycles": cycles, "seconds": dt}))
+""" % (ROOT, seconds_hint)
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=600)
+    if out.returncode != 0:
+        return {"error": out.stderr[-500:]}
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    return {"value": r["dof"] * r["cycles"] / r["seconds"], "unit": "DOF-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{r['cycles']} float64 oracle sawtooth cycle(s) of the same recipe at N=64 "
+                      f"({r['dof']} DOF, p=2, 512 ordinates, 2 groups), numpy single thread, "
+                      f"{r['seconds']:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="c1_mixed")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of it",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2301_09991_amd import ctf
+    from workloads import WORKLOADS, make_inputs
+
+    w = WORKLOADS[args.workload]
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
+                             scatter_order=ss.shape[0] - 1, discretisation=ctf.CONVFEM_PG,
+                             precision=ctf.FP32_IR, n_inner=2)
+    prob = ctf.Problem(cfg, st, ss, src)
+    del st, ss, src
+    psi = prob.zeros()
+    torch.cuda.synchronize()
+    print(f"[bench] workload {w.name}: N={w.N} p={w.p} n_dir={w.n_dir} G={w.G} DOF={w.dof}",
+          file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        prob.mg_cycle(psi)
+    torch.cuda.synchronize()
+    prob.timing_enable(True, capacity=64 * max(args.steps, 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prob.mg_cycle(psi)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    timers = prob.timing_read()
+    prob.timing_enable(False)
+    ms_per_step = 1e3 * dt / args.steps
+    cycles = args.steps * cfg.n_inner
+    value = w.dof * cycles / dt
+    print(f"[bench] {args.steps} steps in {dt:.3f} s ({ms_per_step:.3f} ms/step)", file=sys.stderr,
+          flush=True)
+
+    kernels = {}
+    for name, (ms, n, dropped) in timers.items():
+        if n:
+            kernels[name] = {"avg_ms": ms / n, "launches": n, "total_ms": ms, "dropped": dropped}
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    avg_s = kernels[dom]["avg_ms"] * 1e-3
+    bytes_per, flops_per = algorithmic_cost(dom, w.p)
+    gbs = w.dof * bytes_per / avg_s / 1e9
+    tflops = w.dof * flops_per / avg_s / 1e12
+    valu_peak = FP32_VALU_TFLOPS if dom.endswith("32") else FP64_VALU_TFLOPS
+    hbm_time, alu_time = bytes_per / HBM_PEAK_GBS, flops_per / (valu_peak * 1e3)
+    if hbm_time >= alu_time:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS}
+    else:
+        roof = {"bound": "alu", "achieved": tflops, "peak": valu_peak, "unit": "TFLOP/s",
+                "frac": tflops / valu_peak}
+    roof.update({"traffic": None, "kernel": dom, "algorithmic_bytes_per_dof": bytes_per,
+                 "algorithmic_flops_per_dof": flops_per, "dof_per_launch": w.dof,
+                 "avg_launch_ms": kernels[dom]["avg_ms"]})
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "DOF-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: {w.N}x{w.N} nodes, p={w.p} ConvFEM + non-linear PG, "
+                               f"{w.n_dir} ordinates, {w.G} groups downscatter; step = f64 residual"
+                               f" + {cfg.n_inner} f32 sawtooth cycles + f64 update",
+                   "dof": w.dof, "cycles_per_step": cfg.n_inner, "outer_precision": "f64"},
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -185,6 +185,27 @@ int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_s
 /* ||v||_W of a finest-level array (synchronous). */
 int ctf_norm(ctf_problem* prob, const double* v, double* out);
 
+/* In-library kernel timers (HIP events recorded on the problem's stream around each launch of a
+ * kernel class).  ctf_timing_enable(prob, 1, cap) synchronises, clears the counters and records
+ * at most cap launches per class from then on; (prob, 0, 0) stops recording.
+ * ctf_timing_read synchronises and returns the summed event time (ms) of the recorded launches
+ * of one class, their count, and how many launches were not recorded for lack of capacity. */
+enum {
+  CTF_T_PG64 = 0,      /* finest ConvFEM/PG residual or sweep, float64 */
+  CTF_T_PG32,          /* same, float32 (refinement inner cycles) */
+  CTF_T_UPWIND64,      /* finest upwind residual or sweep, float64 */
+  CTF_T_UPWIND32,
+  CTF_T_CORR0,         /* upwind correction sweeps on the finest level */
+  CTF_T_CORRC,         /* upwind correction sweeps on coarse levels */
+  CTF_T_RESTRICT,
+  CTF_T_MOMENTS,
+  CTF_T_EMISSION,
+  CTF_T_NORM,
+  CTF_T_COUNT
+};
+int ctf_timing_enable(ctf_problem* prob, int on, int capacity);
+int ctf_timing_read(ctf_problem* prob, int cls, double* total_ms, int* launches, int* dropped);
+
 /* Thread-local description of the last error ("" if none). */
 const char* ctf_last_error(void);
 

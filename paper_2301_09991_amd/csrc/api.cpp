@@ -120,6 +120,17 @@ struct ctf_problem {
   Stencils<float> st_f{};
   PGParams pp{};
   int bc_vac = 0;
+  // in-library kernel timers: per kernel class, pairs of events recorded around each launch
+  bool timing = false;
+  int timing_cap = 0;
+  std::vector<hipEvent_t> ev[CTF_T_COUNT];
+  int ev_used[CTF_T_COUNT] = {};
+  int ev_dropped[CTF_T_COUNT] = {};
+
+  ~ctf_problem() {
+    for (auto& v : ev)
+      for (hipEvent_t e : v) (void)hipEventDestroy(e);
+  }
 
   size_t dof(int l) const { return size_t(dims[l].n) * dims[l].n * dims[l].nd * dims[l].G; }
   LevelData<double> ld(int l) const {
@@ -134,6 +145,25 @@ struct ctf_problem {
 };
 
 namespace {
+
+// Records a start/stop event pair on the problem's stream around one kernel launch while the
+// problem's timers are enabled.
+struct Timed {
+  ctf_problem* P;
+  int cls, slot = -1;
+  Timed(ctf_problem* p, int c) : P(p), cls(c) {
+    if (!P->timing) return;
+    if (P->ev_used[cls] >= P->timing_cap) {
+      ++P->ev_dropped[cls];
+      return;
+    }
+    slot = P->ev_used[cls]++;
+    (void)hipEventRecord(P->ev[cls][2 * slot], P->stream);
+  }
+  ~Timed() {
+    if (slot >= 0) (void)hipEventRecord(P->ev[cls][2 * slot + 1], P->stream);
+  }
+};
 
 // Lay out every device array of the problem over the workspace (base == nullptr: sizing pass).
 size_t layout(ctf_problem* P, char* base) {
@@ -208,7 +238,11 @@ int check_level(const ctf_problem* P, int level) {
 // E <- emission of psi (source S if with_source, else none)
 int emission64(ctf_problem* P, const double* psi, bool with_source) {
   const int nl = P->cfg.scatter_order + 1;
-  CTF_HIP(launch_moments<double>(P->ld(0), psi, P->phi, P->nmom, P->stream));
+  {
+    Timed t(P, CTF_T_MOMENTS);
+    CTF_HIP(launch_moments<double>(P->ld(0), psi, P->phi, P->nmom, P->stream));
+  }
+  Timed t(P, CTF_T_EMISSION);
   CTF_HIP(launch_emission<double>(P->dims[0], P->phi, P->sigma_s, nl,
                                   with_source ? P->source : nullptr, P->E, P->stream));
   return CTF_OK;
@@ -219,12 +253,14 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
              double* ky_out) {
   const ctf_config& c = P->cfg;
   if (c.discretisation == CTF_UPWIND) {
+    Timed t(P, CTF_T_UPWIND64);
     CTF_HIP(launch_upwind_full<double>(P->ld(0), P->bc_vac, psi, P->E, P->nmom, out, mode, sign,
                                        nullptr, P->stream));
     return CTF_OK;
   }
   const bool frozen = c.discretisation == CTF_CONVFEM_PG_FROZEN_K;
   if (frozen && !P->k_held) return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
+  Timed t(P, CTF_T_PG64);
   CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, psi, P->E, P->nmom,
                             frozen ? P->kx : nullptr, frozen ? P->ky : nullptr, out, kx_out, ky_out,
                             mode, sign, nullptr, P->stream));
@@ -232,7 +268,10 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
 }
 
 int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
-  CTF_HIP(launch_wnorm2<double>(P->ld(level), v, P->partial, P->npartial, P->scal, P->stream));
+  {
+    Timed t(P, CTF_T_NORM);
+    CTF_HIP(launch_wnorm2<double>(P->ld(level), v, P->partial, P->npartial, P->scal, P->stream));
+  }
   double s2 = 0.0;
   CTF_HIP(hipMemcpyAsync(&s2, P->scal, sizeof(double), hipMemcpyDeviceToHost, P->stream));
   CTF_HIP(hipStreamSynchronize(P->stream));
@@ -252,6 +291,7 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
   for (int s = 0; s < nsweeps; ++s) {
     const bool last = s == nsweeps - 1;
     T* dst = (s % 2 == 0) ? bufa : bufb;
+    Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
     CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, nac, rhs, dst,
                                         (last && acc) ? acc : nullptr, P->stream));
     cur = dst;
@@ -265,8 +305,10 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
 int cycle_rest64(ctf_problem* P, double* psi) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
-  for (int l = 1; l < L; ++l)
+  for (int l = 1; l < L; ++l) {
+    Timed t(P, CTF_T_RESTRICT);
     CTF_HIP(launch_restrict<double>(P->ld(l - 1), P->ld(l), P->rho[l - 1], P->rho[l], P->stream));
+  }
   const double* e = nullptr;
   for (int l = L - 1; l >= 0; --l) {
     const int xmode = (l == L - 1) ? 2 : 1;
@@ -300,18 +342,28 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero) {
     CTF_HIP(hipMemcpyAsync(P->rho_f[0], P->r_f, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice,
                            P->stream));
   } else {
-    CTF_HIP(launch_moments<float>(P->lf(0), P->e_f, P->phi_f, P->nmom, P->stream));
-    CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    {
+      Timed t(P, CTF_T_MOMENTS);
+      CTF_HIP(launch_moments<float>(P->lf(0), P->e_f, P->phi_f, P->nmom, P->stream));
+    }
+    {
+      Timed t(P, CTF_T_EMISSION);
+      CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    }
     if (c.discretisation == CTF_UPWIND) {
+      Timed t(P, CTF_T_UPWIND32);
       CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, P->e_f, P->E_f, P->nmom, P->rho_f[0], 0,
                                         1.0f, P->r_f, P->stream));
     } else {
+      Timed t(P, CTF_T_PG32);
       CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, P->e_f, P->E_f, P->nmom, P->kx_f,
                                P->ky_f, P->rho_f[0], nullptr, nullptr, 0, 1.0f, P->r_f, P->stream));
     }
   }
-  for (int l = 1; l < L; ++l)
+  for (int l = 1; l < L; ++l) {
+    Timed t(P, CTF_T_RESTRICT);
     CTF_HIP(launch_restrict<float>(P->lf(l - 1), P->lf(l), P->rho_f[l - 1], P->rho_f[l], P->stream));
+  }
   const float* e = nullptr;
   for (int l = L - 1; l >= 0; --l) {
     const int xmode = (l == L - 1) ? 2 : 1;
@@ -330,12 +382,20 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero) {
   float* cur = P->e_f;
   float* other = P->e_tmp_f;
   for (int s = 0; s < c.n_pg; ++s) {
-    CTF_HIP(launch_moments<float>(P->lf(0), cur, P->phi_f, P->nmom, P->stream));
-    CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    {
+      Timed t(P, CTF_T_MOMENTS);
+      CTF_HIP(launch_moments<float>(P->lf(0), cur, P->phi_f, P->nmom, P->stream));
+    }
+    {
+      Timed t(P, CTF_T_EMISSION);
+      CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+    }
     if (c.discretisation == CTF_UPWIND) {
+      Timed t(P, CTF_T_UPWIND32);
       CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, cur, P->E_f, P->nmom, other, 1, 1.0f,
                                         P->r_f, P->stream));
     } else {
+      Timed t(P, CTF_T_PG32);
       CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, cur, P->E_f, P->nmom, P->kx_f, P->ky_f,
                                other, nullptr, nullptr, 1, 1.0f, P->r_f, P->stream));
     }
@@ -732,6 +792,42 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
   return status;
+}
+
+int ctf_timing_enable(ctf_problem* P, int on, int capacity) {
+  if (!P || capacity < 0) return fail(CTF_EINVAL, "bad argument");
+  CTF_HIP(hipStreamSynchronize(P->stream));
+  P->timing = false;
+  for (int c = 0; c < CTF_T_COUNT; ++c) {
+    P->ev_used[c] = 0;
+    P->ev_dropped[c] = 0;
+  }
+  if (!on) return CTF_OK;
+  for (int c = 0; c < CTF_T_COUNT; ++c) {
+    while (static_cast<int>(P->ev[c].size()) < 2 * capacity) {
+      hipEvent_t e;
+      CTF_HIP(hipEventCreate(&e));
+      P->ev[c].push_back(e);
+    }
+  }
+  P->timing_cap = capacity;
+  P->timing = true;
+  return CTF_OK;
+}
+
+int ctf_timing_read(ctf_problem* P, int cls, double* total_ms, int* launches, int* dropped) {
+  if (!P || cls < 0 || cls >= CTF_T_COUNT) return fail(CTF_EINVAL, "bad argument");
+  CTF_HIP(hipStreamSynchronize(P->stream));
+  double tot = 0.0;
+  for (int s = 0; s < P->ev_used[cls]; ++s) {
+    float ms = 0.0f;
+    CTF_HIP(hipEventElapsedTime(&ms, P->ev[cls][2 * s], P->ev[cls][2 * s + 1]));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = P->ev_used[cls];
+  if (dropped) *dropped = P->ev_dropped[cls];
+  return CTF_OK;
 }
 
 const char* ctf_last_error(void) { return g_err.c_str(); }

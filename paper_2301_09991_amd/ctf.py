@@ -23,8 +23,10 @@ EXPORTED = [
     "ctf_num_levels", "ctf_level_info", "ctf_level_quadrature", "ctf_convfem_stencils",
     "ctf_level_sigma_t", "ctf_apply_operator", "ctf_moments", "ctf_freeze_k", "ctf_smooth",
     "ctf_restrict", "ctf_prolong", "ctf_mg_cycle", "ctf_solve", "ctf_norm", "ctf_last_error",
-    "ctf_quadrature",
+    "ctf_quadrature", "ctf_timing_enable", "ctf_timing_read",
 ]
+TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
+                 "emission", "norm"]
 
 
 class Config(ctypes.Structure):
@@ -82,6 +84,8 @@ def load():
         "ctf_solve": (I, [P, P, D, I, ctypes.POINTER(SolveInfo)]),
         "ctf_norm": (I, [P, P, ctypes.POINTER(D)]),
         "ctf_last_error": (ctypes.c_char_p, []),
+        "ctf_timing_enable": (I, [P, I, I]),
+        "ctf_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -248,6 +252,19 @@ class Problem:
         return {"converged": rc == CTF_OK, "cycles": info.cycles, "outer_steps": info.outer_steps,
                 "rel_residual": info.rel_residual, "seconds": info.seconds,
                 "history": hist[:n].copy() if history_len else None}
+
+    def timing_enable(self, on=True, capacity=4096):
+        _check(self.lib.ctf_timing_enable(self.handle, int(on), capacity if on else 0))
+
+    def timing_read(self):
+        """{class: (total_ms, launches, dropped)} of the recorded kernel launches."""
+        out = {}
+        for c, name in enumerate(TIMER_CLASSES):
+            ms, n, dr = ctypes.c_double(), ctypes.c_int(), ctypes.c_int()
+            _check(self.lib.ctf_timing_read(self.handle, c, ctypes.byref(ms), ctypes.byref(n),
+                                            ctypes.byref(dr)))
+            out[name] = (ms.value, n.value, dr.value)
+        return out
 
     def norm(self, v):
         r = ctypes.c_double(0.0)
