@@ -2,6 +2,7 @@
 // sawtooth-cycle / refinement drivers that queue the HIP kernels of kernels.hip.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -210,7 +211,7 @@ size_t layout(ctf_problem* P, char* base) {
     P->r_f = c.take<float>(P->dof(0));
   }
   P->npartial = wnorm2_partials(P->dims[0]);
-  P->partial = c.take<double>(P->npartial);
+  P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0])));
   P->scal = c.take<double>(8);
   return c.off + 256;
 }
@@ -248,30 +249,61 @@ int emission64(ctf_problem* P, const double* psi, bool with_source) {
   return CTF_OK;
 }
 
-// out = sign * rho(psi) (mode 0) or out = psi + rho/(beta d) (mode 1), emission already in E
-int finest64(ctf_problem* P, const double* psi, double* out, int mode, double sign, double* kx_out,
-             double* ky_out) {
+// Finest operator with the emission already in E.
+//   mode 0: out = sign * rho(psi) (out and / or out_f), with the squared weighted norm summed into
+//           P->scal[0] when want_norm; mode 1: out = psi + rho / (beta d).
+//   kf: float copies of the diffusivities computed from psi (mixed precision), or null.
+int finest64(ctf_problem* P, const double* psi, double* out, int mode, double sign,
+             float* out_f = nullptr, bool want_norm = false, bool k_float = false) {
   const ctf_config& c = P->cfg;
   if (c.discretisation == CTF_UPWIND) {
-    Timed t(P, CTF_T_UPWIND64);
-    CTF_HIP(launch_upwind_full<double>(P->ld(0), P->bc_vac, psi, P->E, P->nmom, out, mode, sign,
-                                       nullptr, P->stream));
+    if (out_f) return fail(CTF_EUNSUPPORTED, "internal: float output of the upwind operator");
+    {
+      Timed t(P, CTF_T_UPWIND64);
+      CTF_HIP(launch_upwind_full<double>(P->ld(0), P->bc_vac, psi, P->E, P->nmom, out, mode, sign,
+                                         nullptr, P->stream));
+    }
+    if (want_norm) {
+      Timed t(P, CTF_T_NORM);
+      CTF_HIP(launch_wnorm2<double>(P->ld(0), out, P->partial, P->npartial, P->scal, P->stream));
+    }
     return CTF_OK;
   }
   const bool frozen = c.discretisation == CTF_CONVFEM_PG_FROZEN_K;
   if (frozen && !P->k_held) return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
-  Timed t(P, CTF_T_PG64);
-  CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, psi, P->E, P->nmom,
-                            frozen ? P->kx : nullptr, frozen ? P->ky : nullptr, out, kx_out, ky_out,
-                            mode, sign, nullptr, P->stream));
+  PGLaunch<double> o;
+  o.psi = psi;
+  o.E = P->E;
+  o.nmomE = P->nmom;
+  if (frozen) {
+    o.kx_in = P->kx;
+    o.ky_in = P->ky;
+  } else {
+    o.kx_out = P->kx;
+    o.ky_out = P->ky;
+    if (k_float) {
+      o.kx_out_f = P->kx_f;
+      o.ky_out_f = P->ky_f;
+    }
+  }
+  o.out = out;
+  o.out_f = out_f;
+  o.mode = mode;
+  o.sign = sign;
+  o.partial = (mode == 0 && want_norm) ? P->partial : nullptr;
+  {
+    Timed t(P, CTF_T_PG64);
+    CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, o, P->stream));
+  }
+  if (o.partial) {
+    Timed t(P, CTF_T_NORM);
+    CTF_HIP(launch_sum_partials(P->partial, int(pg_partials(P->dims[0])), P->scal, P->stream));
+  }
   return CTF_OK;
 }
 
-int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
-  {
-    Timed t(P, CTF_T_NORM);
-    CTF_HIP(launch_wnorm2<double>(P->ld(level), v, P->partial, P->npartial, P->scal, P->stream));
-  }
+// sqrt of the squared norm in P->scal[0] (synchronous)
+int read_norm(ctf_problem* P, double* out_host) {
   double s2 = 0.0;
   CTF_HIP(hipMemcpyAsync(&s2, P->scal, sizeof(double), hipMemcpyDeviceToHost, P->stream));
   CTF_HIP(hipStreamSynchronize(P->stream));
@@ -280,17 +312,27 @@ int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
   return CTF_OK;
 }
 
+int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
+  {
+    Timed t(P, CTF_T_NORM);
+    CTF_HIP(launch_wnorm2<double>(P->ld(level), v, P->partial, P->npartial, P->scal, P->stream));
+  }
+  return read_norm(P, out_host);
+}
+
 // n upwind correction sweeps on level l: the first from (xmode, xsrc), result pointer returned;
-// acc != null: the last sweep adds into acc instead of writing a buffer.
+// acc != null: the last sweep adds into acc instead of writing a buffer; final != null: the last
+// sweep writes there.
 template <typename T>
 int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsrc, int xmode,
-                      const T* rhs, int nsweeps, T* bufa, T* bufb, T* acc, const T** result) {
+                      const T* rhs, int nsweeps, T* bufa, T* bufb, T* acc, const T** result,
+                      T* final = nullptr) {
   const int nac = (l + 1 < P->L) ? P->dims[l + 1].na : 1;
   const T* cur = xsrc;
   int mode = xmode;
   for (int s = 0; s < nsweeps; ++s) {
     const bool last = s == nsweeps - 1;
-    T* dst = (s % 2 == 0) ? bufa : bufb;
+    T* dst = (last && final) ? final : ((s % 2 == 0) ? bufa : bufb);
     Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
     CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, nac, rhs, dst,
                                         (last && acc) ? acc : nullptr, P->stream));
@@ -322,7 +364,7 @@ int cycle_rest64(ctf_problem* P, double* psi) {
   for (int s = 0; s < c.n_pg; ++s) {
     int rc = emission64(P, cur, true);
     if (rc) return rc;
-    rc = finest64(P, cur, other, 1, 1.0, nullptr, nullptr);
+    rc = finest64(P, cur, other, 1, 1.0);
     if (rc) return rc;
     std::swap(cur, other);
   }
@@ -332,95 +374,113 @@ int cycle_rest64(ctf_problem* P, double* psi) {
 }
 
 // ---- mixed precision: one float32 cycle on the correction equation A_k e = r --------------------
-// r (float32, P->r_f) is the float64 residual rounded; k is frozen at the outer psi; e in P->e_f.
+// r (float32, P->r_f) is the float64 residual rounded; k is frozen at the outer psi (float32 in
+// kx_f, ky_f); e in P->e_f.
+int inner_finest32(ctf_problem* P, const float* e, float* out, int mode) {
+  const ctf_config& c = P->cfg;
+  const int nl = c.scatter_order + 1;
+  {
+    Timed t(P, CTF_T_MOMENTS);
+    CTF_HIP(launch_moments<float>(P->lf(0), e, P->phi_f, P->nmom, P->stream));
+  }
+  {
+    Timed t(P, CTF_T_EMISSION);
+    CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
+  }
+  if (c.discretisation == CTF_UPWIND) {
+    Timed t(P, CTF_T_UPWIND32);
+    CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, e, P->E_f, P->nmom, out, mode, 1.0f,
+                                      P->r_f, P->stream));
+    return CTF_OK;
+  }
+  PGLaunch<float> o;
+  o.psi = e;
+  o.E = P->E_f;
+  o.nmomE = P->nmom;
+  o.kx_in = P->kx_f;
+  o.ky_in = P->ky_f;
+  o.out = out;
+  o.rhs = P->r_f;
+  o.mode = mode;
+  Timed t(P, CTF_T_PG32);
+  CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, o, P->stream));
+  return CTF_OK;
+}
+
 int inner_cycle32(ctf_problem* P, bool e_is_zero) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
-  const int nl = c.scatter_order + 1;
-  // inner residual r - A e
-  if (e_is_zero) {
-    CTF_HIP(hipMemcpyAsync(P->rho_f[0], P->r_f, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice,
-                           P->stream));
-  } else {
-    {
-      Timed t(P, CTF_T_MOMENTS);
-      CTF_HIP(launch_moments<float>(P->lf(0), P->e_f, P->phi_f, P->nmom, P->stream));
-    }
-    {
-      Timed t(P, CTF_T_EMISSION);
-      CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
-    }
-    if (c.discretisation == CTF_UPWIND) {
-      Timed t(P, CTF_T_UPWIND32);
-      CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, P->e_f, P->E_f, P->nmom, P->rho_f[0], 0,
-                                        1.0f, P->r_f, P->stream));
-    } else {
-      Timed t(P, CTF_T_PG32);
-      CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, P->e_f, P->E_f, P->nmom, P->kx_f,
-                               P->ky_f, P->rho_f[0], nullptr, nullptr, 0, 1.0f, P->r_f, P->stream));
-    }
+  // inner residual r - A e (just r while e = 0)
+  const float* r0 = P->r_f;
+  if (!e_is_zero) {
+    int rc = inner_finest32(P, P->e_f, P->rho_f[0], 0);
+    if (rc) return rc;
+    r0 = P->rho_f[0];
   }
   for (int l = 1; l < L; ++l) {
     Timed t(P, CTF_T_RESTRICT);
-    CTF_HIP(launch_restrict<float>(P->lf(l - 1), P->lf(l), P->rho_f[l - 1], P->rho_f[l], P->stream));
+    CTF_HIP(launch_restrict<float>(P->lf(l - 1), P->lf(l), l == 1 ? r0 : P->rho_f[l - 1], P->rho_f[l],
+                                   P->stream));
   }
   const float* e = nullptr;
   for (int l = L - 1; l >= 0; --l) {
     const int xmode = (l == L - 1) ? 2 : 1;
-    if (l == 0 && e_is_zero) {
-      // e = 0 before this cycle: the correction sweeps' result is the new e itself
-      int rc = correction_sweeps<float>(P, P->lf(0), 0, e, xmode, P->rho_f[0], c.n_jacobi,
-                                        P->ea_f[0], P->eb_f[0], nullptr, &e);
-      if (rc) return rc;
-      CTF_HIP(hipMemcpyAsync(P->e_f, e, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
-    } else {
-      int rc = correction_sweeps<float>(P, P->lf(l), l, e, xmode, P->rho_f[l], c.n_jacobi,
-                                        P->ea_f[l], P->eb_f[l], l == 0 ? P->e_f : nullptr, &e);
-      if (rc) return rc;
-    }
+    const float* rhs = l == 0 ? r0 : P->rho_f[l];
+    // e = 0 before the cycle: the finest correction is the new e itself (written to e_f);
+    // otherwise the last finest sweep adds into e_f
+    int rc = correction_sweeps<float>(P, P->lf(l), l, e, xmode, rhs, c.n_jacobi, P->ea_f[l],
+                                      P->eb_f[l], (l == 0 && !e_is_zero) ? P->e_f : nullptr, &e,
+                                      (l == 0 && e_is_zero) ? P->e_f : nullptr);
+    if (rc) return rc;
   }
   float* cur = P->e_f;
   float* other = P->e_tmp_f;
   for (int s = 0; s < c.n_pg; ++s) {
-    {
-      Timed t(P, CTF_T_MOMENTS);
-      CTF_HIP(launch_moments<float>(P->lf(0), cur, P->phi_f, P->nmom, P->stream));
-    }
-    {
-      Timed t(P, CTF_T_EMISSION);
-      CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
-    }
-    if (c.discretisation == CTF_UPWIND) {
-      Timed t(P, CTF_T_UPWIND32);
-      CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, cur, P->E_f, P->nmom, other, 1, 1.0f,
-                                        P->r_f, P->stream));
-    } else {
-      Timed t(P, CTF_T_PG32);
-      CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, cur, P->E_f, P->nmom, P->kx_f, P->ky_f,
-                               other, nullptr, nullptr, 1, 1.0f, P->r_f, P->stream));
-    }
+    int rc = inner_finest32(P, cur, other, 1);
+    if (rc) return rc;
     std::swap(cur, other);
   }
-  if (cur != P->e_f)
-    CTF_HIP(hipMemcpyAsync(P->e_f, cur, P->dof(0) * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+  if (cur != P->e_f) std::swap(P->e_f, P->e_tmp_f);  // the result buffer becomes e_f
   return CTF_OK;
 }
 
-// float64 residual of psi into rho[0]; for ConvFEM also the diffusivities of psi (for the inner
-// float32 cycles).  Returns ||rho||_W / ||b||_W through rel.
-int outer_residual(ctf_problem* P, const double* psi, double* rel, bool keep_k) {
+// float64 residual of psi, rounded to float32 into r_f (and kept in float64 in rho[0] for the
+// upwind / frozen-k discretisations); the diffusivities of psi go to kx_f, ky_f for the inner
+// float32 cycles.  Returns ||rho||_W / ||b||_W through rel.
+int outer_residual(ctf_problem* P, const double* psi, double* rel) {
   int rc = emission64(P, psi, true);
   if (rc) return rc;
-  const bool pg = P->cfg.discretisation != CTF_UPWIND;
-  const bool frozen = P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K;
-  double* kxo = (pg && keep_k && !frozen) ? P->kx : nullptr;
-  double* kyo = (pg && keep_k && !frozen) ? P->ky : nullptr;
-  rc = finest64(P, psi, P->rho[0], 0, 1.0, kxo, kyo);
-  if (rc) return rc;
+  const int disc = P->cfg.discretisation;
+  const size_t n = P->dof(0);
   double nr = 0.0;
-  rc = wnorm64(P, 0, P->rho[0], &nr);
+  if (disc == CTF_CONVFEM_PG) {
+    rc = finest64(P, psi, nullptr, 0, 1.0, P->r_f, true, true);
+    if (rc) return rc;
+    rc = read_norm(P, &nr);
+  } else {
+    rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true, false);
+    if (rc) return rc;
+    CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
+    if (disc == CTF_CONVFEM_PG_FROZEN_K) {
+      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
+      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
+    }
+    if (!rc) rc = read_norm(P, &nr);
+  }
   if (rc) return rc;
   *rel = nr / P->bnorm;
+  return CTF_OK;
+}
+
+// one refinement step after outer_residual: n_inner float32 cycles and the float64 update
+int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done) {
+  int it = 0;
+  for (; it < P->cfg.n_inner && it < max_inner; ++it) {
+    int rc = inner_cycle32(P, it == 0);
+    if (rc) return rc;
+  }
+  if (it > 0) CTF_HIP(launch_add_f2d(psi, P->e_f, P->dof(0), P->stream));
+  if (done) *done = it;
   return CTF_OK;
 }
 
@@ -622,7 +682,7 @@ int ctf_apply_operator(ctf_problem* P, const double* psi, double* out, int mode)
   if (psi == out) return fail(CTF_EINVAL, "psi and out must not alias");
   int rc = emission64(P, psi, mode == CTF_OP_RESIDUAL);
   if (rc) return rc;
-  return finest64(P, psi, out, 0, mode == CTF_OP_RESIDUAL ? 1.0 : -1.0, nullptr, nullptr);
+  return finest64(P, psi, out, 0, mode == CTF_OP_RESIDUAL ? 1.0 : -1.0);
 }
 
 int ctf_moments(ctf_problem* P, const double* psi, double* phi) {
@@ -636,8 +696,17 @@ int ctf_freeze_k(ctf_problem* P, const double* psi, double* kx, double* ky) {
   if (P->cfg.discretisation == CTF_UPWIND) return fail(CTF_EINVAL, "upwind has no diffusivities");
   int rc = emission64(P, psi, true);
   if (rc) return rc;
-  CTF_HIP(launch_pg<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, psi, P->E, P->nmom, nullptr, nullptr,
-                            P->psi_tmp, P->kx, P->ky, 0, 1.0, nullptr, P->stream));
+  PGLaunch<double> o;
+  o.psi = psi;
+  o.E = P->E;
+  o.nmomE = P->nmom;
+  o.kx_out = P->kx;
+  o.ky_out = P->ky;
+  o.out = P->psi_tmp;
+  {
+    Timed t(P, CTF_T_PG64);
+    CTF_HIP(launch_pg<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, o, P->stream));
+  }
   P->k_held = true;
   const size_t bytes = P->dof(0) * sizeof(double);
   if (kx) CTF_HIP(hipMemcpyAsync(kx, P->kx, bytes, hipMemcpyDeviceToDevice, P->stream));
@@ -666,7 +735,7 @@ int ctf_smooth(ctf_problem* P, int level, int kind, double* x, const double* rhs
     for (int s = 0; s < nsweeps; ++s) {
       rc = emission64(P, cur, true);
       if (rc) return rc;
-      rc = finest64(P, cur, other, 1, 1.0, nullptr, nullptr);
+      rc = finest64(P, cur, other, 1, 1.0);
       if (rc) return rc;
       std::swap(cur, other);
     }
@@ -700,36 +769,23 @@ int ctf_norm(ctf_problem* P, const double* v, double* out) {
 
 int ctf_mg_cycle(ctf_problem* P, double* psi, double* rel_res) {
   if (!P || !psi) return fail(CTF_EINVAL, "null argument");
+  if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !P->k_held)
+    return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
   if (P->mixed()) {
     // one refinement step: float64 residual, n_inner float32 cycles, float64 update
     double rel = 0.0;
-    int rc = outer_residual(P, psi, &rel, true);
+    int rc = outer_residual(P, psi, &rel);
     if (rc) return rc;
     if (rel_res) *rel_res = rel;
-    const size_t n = P->dof(0);
-    CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
-    if (P->cfg.discretisation != CTF_UPWIND && P->cfg.discretisation != CTF_CONVFEM_PG_FROZEN_K) {
-      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
-      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
-    } else if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K) {
-      if (!P->k_held) return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
-      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
-      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
-    }
-    for (int it = 0; it < P->cfg.n_inner; ++it) {
-      rc = inner_cycle32(P, it == 0);
-      if (rc) return rc;
-    }
-    CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
-    return CTF_OK;
+    return refine_rest(P, psi, P->cfg.n_inner, nullptr);
   }
   int rc = emission64(P, psi, true);
   if (rc) return rc;
-  rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, nullptr);
+  rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, rel_res != nullptr);
   if (rc) return rc;
   if (rel_res) {
     double nr = 0.0;
-    rc = wnorm64(P, 0, P->rho[0], &nr);
+    rc = read_norm(P, &nr);
     if (rc) return rc;
     *rel_res = nr / P->bnorm;
   }
@@ -738,6 +794,8 @@ int ctf_mg_cycle(ctf_problem* P, double* psi, double* rel_res) {
 
 int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solve_info* info) {
   if (!P || !psi || max_cycles < 0) return fail(CTF_EINVAL, "bad argument");
+  if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !P->k_held)
+    return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
   const auto t0 = std::chrono::steady_clock::now();
   int cycles = 0, outer = 0, nhist = 0;
   double rel = 0.0;
@@ -745,13 +803,13 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
   for (;;) {
     int rc;
     if (P->mixed()) {
-      rc = outer_residual(P, psi, &rel, true);
+      rc = outer_residual(P, psi, &rel);
     } else {
       rc = emission64(P, psi, true);
-      if (!rc) rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, nullptr);
+      if (!rc) rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true);
       if (!rc) {
         double nr = 0.0;
-        rc = wnorm64(P, 0, P->rho[0], &nr);
+        rc = read_norm(P, &nr);
         rel = nr / P->bnorm;
       }
     }
@@ -764,19 +822,10 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
     }
     if (cycles >= max_cycles) break;
     if (P->mixed()) {
-      const size_t n = P->dof(0);
-      CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
-      if (P->cfg.discretisation != CTF_UPWIND) {
-        if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !P->k_held)
-          return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
-        CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
-        CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
-      }
-      for (int it = 0; it < P->cfg.n_inner && cycles < max_cycles; ++it, ++cycles) {
-        rc = inner_cycle32(P, it == 0);
-        if (rc) return rc;
-      }
-      CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
+      int done = 0;
+      rc = refine_rest(P, psi, max_cycles - cycles, &done);
+      if (rc) return rc;
+      cycles += done;
       ++outer;
     } else {
       rc = cycle_rest64(P, psi);

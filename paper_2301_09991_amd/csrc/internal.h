@@ -80,14 +80,34 @@ hipError_t launch_emission(const LevelDims& d, const T* phi, const T* sigma_s, i
                            const T* source, T* E, hipStream_t s);
 
 // Finest ConvFEM Petrov-Galerkin operator.
-//   mode 0: out = sign * rho;   mode 1: out = psi + rho / (beta d)
-//   kx, ky != null: frozen diffusivities (else computed from psi)
-//   kx_out, ky_out != null: store the diffusivities computed from psi (mode 0 only)
+//   mode 0: out = sign * rho (out and / or out_f; partial: per-block sum of w_n h^2 out^2)
+//   mode 1: out = psi + rho / (beta d)
+//   kx_in, ky_in != null: these diffusivities (frozen); else k is computed from psi into
+//   kx_out, ky_out (required), plus float copies in kx_out_f, ky_out_f if non-null
 //   rhs != null: a per-DOF term added to the emission (right-hand side of a correction equation)
 template <typename T>
+struct PGLaunch {
+  const T* psi = nullptr;
+  const T* E = nullptr;
+  int nmomE = 1;
+  const T* kx_in = nullptr;
+  const T* ky_in = nullptr;
+  T* out = nullptr;
+  float* out_f = nullptr;
+  double* partial = nullptr;
+  T* kx_out = nullptr;
+  T* ky_out = nullptr;
+  float* kx_out_f = nullptr;
+  float* ky_out_f = nullptr;
+  const T* rhs = nullptr;
+  int mode = 0;
+  T sign = T(1);
+};
+template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
-                     const T* psi, const T* E, int nmomE, const T* kx, const T* ky, T* out,
-                     T* kx_out, T* ky_out, int mode, T sign, const T* rhs, hipStream_t s);
+                     const PGLaunch<T>& o, hipStream_t s);
+// number of per-block partial sums a mode-0 launch_pg writes
+size_t pg_partials(const LevelDims& d);
 
 // Finest upwind operator: mode 0 out = sign * rho, mode 1 out = psi + rho / d.
 template <typename T>
@@ -113,6 +133,8 @@ template <typename T>
 hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int npartial,
                          double* out, hipStream_t s);
 int wnorm2_partials(const LevelDims& d);
+// out[0] = sum of np partials in a fixed order
+hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s);
 
 template <typename T>
 hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s);

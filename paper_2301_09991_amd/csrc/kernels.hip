@@ -94,15 +94,7 @@ __global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __res
 }
 
 // ---------------------------------------------------------------------------------------------
-// ConvFEM Petrov-Galerkin residual (eq. Petrov) of one 16 x 16 tile, one ordinate, one group.
-//   psi is staged with a 3P halo (halo rule above); Psi_x = f(psi; m (x) d), Psi_y = f(psi; d (x) m)
-//   on the tile + 2P ring; the anisotropic diffusivities (eq. ano-k) on the tile + P ring at the
-//   clamped position (the k halo copies the nearest interior value); then
-//   rho = q - mu Psi_x - nu Psi_y - kDiff_x - kDiff_y - sigma_t psi  with
-//   kDiff(psi; k, w) = sum_o w_o (k_c + k_o)(psi_o - psi_c)  (= f(k psi; w) + k f(psi; w) - psi f(k; w)
-//   since every w_Diff sums to zero).
-constexpr int kTile = 16;
-
+// ConvFEM Petrov-Galerkin operator (eq. Petrov, eqs. kxx/kyy, eq. ano-k), arguments.
 template <typename T>
 struct PGArgs {
   LevelData<T> L;
@@ -121,123 +113,237 @@ struct PGArgs {
   int mode;
   T sign;
   int ntx;
+  float* out_f;       // optional float copy of the output (mode 0)
+  double* partial;    // optional per-block sum of w_n h^2 out^2 (mode 0)
+  float* kx_out_f;    // optional float copies of the computed diffusivities
+  float* ky_out_f;
 };
 
-template <int P, typename T>
-__global__ __launch_bounds__(kBlock) void k_pg(PGArgs<T> a) {
-  constexpr int EXT = kTile + 6 * P;
-  constexpr int GR = kTile + 4 * P;
-  constexpr int KR = kTile + 2 * P;
-  __shared__ T sp[EXT * EXT];
-  __shared__ T sgx[GR * GR];
-  __shared__ T sgy[GR * GR];
-  __shared__ T skx[KR * KR];
-  __shared__ T sky[KR * KR];
+// ---------------------------------------------------------------------------------------------
+// Streaming forms of the ConvFEM Petrov-Galerkin operator.  One wavefront owns a strip of 64
+// columns and marches down its rows; every filter is applied as an x-pass on the current row
+// (row buffer in LDS) followed by a y-pass over a rolling window of x-pass results held in
+// registers, so every input value is read from HBM about once.
+constexpr int kStripW = 64;
+constexpr int kStripH = 32;
 
+template <typename T, int W>
+__device__ __forceinline__ void push(T (&w)[W], T v) {
+#pragma unroll
+  for (int t = 0; t < W - 1; ++t) w[t] = w[t + 1];
+  w[W - 1] = v;
+}
+
+template <typename T, int W>
+__device__ __forceinline__ T ypass(const T (&w)[W], const T* c) {
+  T s = 0;
+#pragma unroll
+  for (int t = 0; t < W; ++t) s += c[t] * w[t];
+  return s;
+}
+
+// Residual with given diffusivities (k_x, k_y read with a copied halo):
+//   rho = rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
+//   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
+template <int P, typename T>
+__global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
+  constexpr int W = 2 * P + 1;
+  constexpr int RW = kStripW + 2 * P;
+  __shared__ T s_psi[RW];
+  __shared__ T s_kx[RW];
+  __shared__ T s_ky[RW];
   const int n = a.L.dims.n;
+  const int lane = threadIdx.x;
+  const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * kStripH;
   const int dir = blockIdx.y, g = blockIdx.z;
-  const int tid = threadIdx.x;
-  const int i0 = (blockIdx.x % a.ntx) * kTile, j0 = (blockIdx.x / a.ntx) * kTile;
   const size_t ncell = size_t(n) * n;
   const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
   const T mu = a.L.mu[dir], nu = a.L.nu[dir];
   const T h = T(a.L.dims.h);
   const T* __restrict__ psi = a.psi + base;
-
-  for (int idx = tid; idx < EXT * EXT; idx += kBlock) {
-    const int ly = idx / EXT, lx = idx - ly * EXT;
-    const int gi = i0 - 3 * P + lx, gj = j0 - 3 * P + ly;
-    T v = T(0);
-    if (!halo_zero(gi, gj, n, mu, nu, a.bc_vac))
-      v = psi[size_t(clampi(gj, 0, n - 1)) * n + clampi(gi, 0, n - 1)];
-    sp[idx] = v;
+  const T* __restrict__ kxin = a.kx_in + base;
+  const T* __restrict__ kyin = a.ky_in + base;
+  T cm[W], cd[W], ck[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    cm[t] = a.st.m[t];
+    cd[t] = a.st.d[t];
+    ck[t] = a.st.k[t];
   }
-  __syncthreads();
-
-  for (int idx = tid; idx < GR * GR; idx += kBlock) {
-    const int ly = idx / GR, lx = idx - ly * GR;
-    T gx = 0, gy = 0;
-#pragma unroll
-    for (int v = -P; v <= P; ++v) {
-      const T* row = sp + (ly + P + v) * EXT + lx + P;
-#pragma unroll
-      for (int u = -P; u <= P; ++u) {
-        const T val = row[u];
-        gx += a.st.m[v + P] * a.st.d[u + P] * val;
-        gy += a.st.d[v + P] * a.st.m[u + P] * val;
-      }
+  T wXd[W] = {}, wXm[W] = {}, wXk[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA2y[W] = {}, wA3y[W] = {};
+  T cpsi[P + 1] = {}, ckx[P + 1] = {}, cky[P + 1] = {};
+  const int gi = x0 + lane;
+  const int c0 = x0 - P + lane, c1 = c0 + kStripW;
+  const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
+  const bool zx0 = (c0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c0 >= n && (a.bc_vac & 2) && mu < T(0));
+  const bool zx1 = (c1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c1 >= n && (a.bc_vac & 2) && mu < T(0));
+  const int yend = min(y0 + kStripH, n);
+  const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
+  double acc = 0.0;
+  for (int r = y0 - P; r < yend + P; ++r) {
+    const int cr = clampi(r, 0, n - 1);
+    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+    const size_t ro = size_t(cr) * n;
+    s_psi[lane] = (zy || zx0) ? T(0) : psi[ro + cc0];
+    s_kx[lane] = kxin[ro + cc0];
+    s_ky[lane] = kyin[ro + cc0];
+    if (lane < 2 * P) {
+      s_psi[kStripW + lane] = (zy || zx1) ? T(0) : psi[ro + cc1];
+      s_kx[kStripW + lane] = kxin[ro + cc1];
+      s_ky[kStripW + lane] = kyin[ro + cc1];
     }
-    sgx[idx] = gx;
-    sgy[idx] = gy;
-  }
-  __syncthreads();
-
-  for (int idx = tid; idx < KR * KR; idx += kBlock) {
-    const int ly = idx / KR, lx = idx - ly * KR;
-    const int ci = clampi(i0 - P + lx, 0, n - 1), cj = clampi(j0 - P + ly, 0, n - 1);
-    T kx, ky;
-    if (a.kx_in) {
-      kx = a.kx_in[base + size_t(cj) * n + ci];
-      ky = a.ky_in[base + size_t(cj) * n + ci];
-    } else {
-      const int cx = ci - i0 + 2 * P, cy = cj - j0 + 2 * P;
-      T mx = 0, my = 0;
+    __syncthreads();
+    T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
 #pragma unroll
-      for (int v = -P; v <= P; ++v)
-#pragma unroll
-        for (int u = -P; u <= P; ++u) {
-          const T mm = a.st.m[v + P] * a.st.m[u + P];
-          mx += mm * sgx[(cy + v) * GR + cx + u];
-          my += mm * sgy[(cy + v) * GR + cx + u];
-        }
-      const T px = sgx[cy * GR + cx], py = sgy[cy * GR + cx];
-      const T rx = a.alpha_r * mu * (mx - px);
-      const T ry = a.alpha_r * nu * (my - py);
-      const T kxabs = a.akabs * tabs(rx) * h / (a.eps_k + tabs(px));
-      const T kyabs = a.akabs * tabs(ry) * h / (a.eps_k + tabs(py));
-      const T kxsq = a.aksq * rx * rx * h / (a.eps_k + tabs(mu) * px * px);
-      const T kysq = a.aksq * ry * ry * h / (a.eps_k + tabs(nu) * py * py);
-      kx = tmin(tmin(h * tabs(mu), kxabs), kxsq);
-      ky = tmin(tmin(h * tabs(nu), kyabs), kysq);
+    for (int u = 0; u < W; ++u) {
+      const T v = s_psi[lane + u], kv = s_kx[lane + u], qv = s_ky[lane + u];
+      xd += cd[u] * v;
+      xm += cm[u] * v;
+      xk += ck[u] * v;
+      a2x += ck[u] * (kv * v);
+      a3x += ck[u] * kv;
+      a2y += cm[u] * (qv * v);
+      a3y += cm[u] * qv;
     }
-    skx[idx] = kx;
-    sky[idx] = ky;
-  }
-  __syncthreads();
-
-  {
-    const int ly = tid / kTile, lx = tid - ly * kTile;
-    const int gi = i0 + lx, gj = j0 + ly;
-    if (gi < n && gj < n) {
-      const T pc = sp[(ly + 3 * P) * EXT + lx + 3 * P];
-      const T kxc = skx[(ly + P) * KR + lx + P], kyc = sky[(ly + P) * KR + lx + P];
-      T dx = 0, dy = 0;
-#pragma unroll
-      for (int v = -P; v <= P; ++v)
-#pragma unroll
-        for (int u = -P; u <= P; ++u) {
-          const T dp = sp[(ly + 3 * P + v) * EXT + lx + 3 * P + u] - pc;
-          const int kk = (ly + P + v) * KR + lx + P + u;
-          dx += a.st.m[v + P] * a.st.k[u + P] * (kxc + skx[kk]) * dp;
-          dy += a.st.k[v + P] * a.st.m[u + P] * (kyc + sky[kk]) * dp;
-        }
-      const size_t cell = size_t(gj) * n + gi;
+    push(cpsi, s_psi[lane + P]);
+    push(ckx, s_kx[lane + P]);
+    push(cky, s_ky[lane + P]);
+    __syncthreads();
+    push(wXd, xd);
+    push(wXm, xm);
+    push(wXk, xk);
+    push(wA2x, a2x);
+    push(wA3x, a3x);
+    push(wA2y, a2y);
+    push(wA3y, a3y);
+    const int o = r - P;
+    if (o >= y0 && gi < n) {
+      const T px = ypass(wXd, cm), py = ypass(wXm, cd);
+      const T pc = cpsi[0];
+      const T dx = ckx[0] * ypass(wXk, cm) + ypass(wA2x, cm) - pc * ypass(wA3x, cm);
+      const T dy = cky[0] * ypass(wXm, ck) + ypass(wA2y, ck) - pc * ypass(wA3y, ck);
+      const size_t cell = size_t(o) * n + gi;
       const size_t eb = size_t(g) * a.nmomE * ncell + cell;
       T q = a.E[eb];
       if (a.nmomE > 1) q += mu * a.E[eb + ncell] + nu * a.E[eb + 2 * ncell];
       if (a.rhs) q += a.rhs[base + cell];
       const T sig = a.L.sigma_t[size_t(g) * ncell + cell];
-      const T px = sgx[(ly + 2 * P) * GR + lx + 2 * P], py = sgy[(ly + 2 * P) * GR + lx + 2 * P];
       const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
       if (a.mode == 0) {
-        a.out[base + cell] = a.sign * rho;
-        if (a.kx_out) {
-          a.kx_out[base + cell] = kxc;
-          a.ky_out[base + cell] = kyc;
-        }
+        const T val = a.sign * rho;
+        if (a.out) a.out[base + cell] = val;
+        if (a.out_f) a.out_f[base + cell] = float(val);
+        acc += double(val) * double(val);
       } else {
-        const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h + sig);
-        a.out[base + cell] = pc + rho / diag;
+        a.out[base + cell] = pc + rho / (diag + a.beta * sig);
+      }
+    }
+  }
+  if (a.partial) {
+    // wave-level reduction in a fixed order (deterministic)
+    __shared__ double red[kStripW];
+    red[lane] = acc;
+    __syncthreads();
+    for (int s = kStripW / 2; s > 0; s >>= 1) {
+      if (lane < s) red[lane] += red[lane + s];
+      __syncthreads();
+    }
+    if (lane == 0) {
+      const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
+      a.partial[b] = red[0] * double(a.L.w[dir]) * a.L.dims.h * a.L.dims.h;
+    }
+  }
+}
+
+// Anisotropic diffusivities of psi (eq. ano-k) on the interior:
+//   Psi_x = f(psi; m (x) d), Psi_y = f(psi; d (x) m) (psi with its halo rule),
+//   R = alpha_r mu (f(Psi; m (x) m) - Psi),  k = min(h|mu|, akabs |R| h/(eps+|Psi|), aksq R^2 h/(eps+|mu| Psi^2)).
+// The strip reads 64 + 4P columns, and writes k for its inner 64 - 2P columns.
+template <int P, typename T>
+__global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
+  constexpr int W = 2 * P + 1;
+  constexpr int RW = kStripW + 2 * P;
+  constexpr int OW = kStripW - 2 * P;   // columns written per strip
+  __shared__ T s_psi[RW];
+  __shared__ T s_gx[kStripW];
+  __shared__ T s_gy[kStripW];
+  const int n = a.L.dims.n;
+  const int lane = threadIdx.x;
+  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * kStripH;
+  const int x0 = xs - P;                 // column of lane 0 (Psi is formed for x0 .. x0 + 63)
+  const int dir = blockIdx.y, g = blockIdx.z;
+  const size_t ncell = size_t(n) * n;
+  const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
+  const T mu = a.L.mu[dir], nu = a.L.nu[dir];
+  const T h = T(a.L.dims.h);
+  const T* __restrict__ psi = a.psi + base;
+  T cm[W], cd[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    cm[t] = a.st.m[t];
+    cd[t] = a.st.d[t];
+  }
+  T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
+  T cgx[P + 1] = {}, cgy[P + 1] = {};
+  const int c0 = x0 - P + lane, c1 = c0 + kStripW;
+  const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
+  const bool zx0 = (c0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c0 >= n && (a.bc_vac & 2) && mu < T(0));
+  const bool zx1 = (c1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c1 >= n && (a.bc_vac & 2) && mu < T(0));
+  const int gi = x0 + lane;
+  const bool writer = lane >= P && lane < kStripW - P && gi < n && gi < xs + OW;
+  const int yend = min(y0 + kStripH, n);
+  const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
+  for (int r = y0 - 2 * P; r < yend + 2 * P; ++r) {
+    const int cr = clampi(r, 0, n - 1);
+    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+    const size_t ro = size_t(cr) * n;
+    s_psi[lane] = (zy || zx0) ? T(0) : psi[ro + cc0];
+    if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : psi[ro + cc1];
+    __syncthreads();
+    T xd = 0, xm = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) {
+      const T v = s_psi[lane + u];
+      xd += cd[u] * v;
+      xm += cm[u] * v;
+    }
+    push(wXd, xd);
+    push(wXm, xm);
+    // Psi on row r - P (valid once the window is full)
+    const T gx = ypass(wXd, cm), gy = ypass(wXm, cd);
+    s_gx[lane] = gx;
+    s_gy[lane] = gy;
+    push(cgx, gx);
+    push(cgy, gy);
+    __syncthreads();
+    T mx = 0, my = 0;
+    if (lane >= P && lane < kStripW - P) {
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        mx += cm[u] * s_gx[lane - P + u];
+        my += cm[u] * s_gy[lane - P + u];
+      }
+    }
+    push(wMx, mx);
+    push(wMy, my);
+    __syncthreads();
+    const int o = r - 2 * P;
+    if (o >= y0 && writer) {
+      const T px = cgx[0], py = cgy[0];
+      const T rx = ar * mu * (ypass(wMx, cm) - px);
+      const T ry = ar * nu * (ypass(wMy, cm) - py);
+      const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
+                        aksq * rx * rx * h / (eps + tabs(mu) * px * px));
+      const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
+                        aksq * ry * ry * h / (eps + tabs(nu) * py * py));
+      const size_t cell = size_t(o) * n + gi;
+      if (a.kx_out) {
+        a.kx_out[base + cell] = kx;
+        a.ky_out[base + cell] = ky;
+      }
+      if (a.kx_out_f) {
+        a.kx_out_f[base + cell] = float(kx);
+        a.ky_out_f[base + cell] = float(ky);
       }
     }
   }
@@ -253,12 +359,11 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
                                                          const T* __restrict__ rhs) {
   const int n = L.dims.n, nd = L.dims.nd;
   const size_t ncell = size_t(n) * n;
-  const size_t total = ncell * nd * L.dims.G;
-  const size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const size_t gn = idx / ncell, cell = idx - gn * ncell;
-  const int g = int(gn / nd), dir = int(gn - size_t(g) * nd);
-  const int j = int(cell / n), i = int(cell - size_t(j) * n);
+  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (cell >= int(ncell)) return;
+  const int dir = blockIdx.y, g = blockIdx.z;
+  const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
+  const int j = cell / n, i = cell - j * n;
   const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
   const T pc = psi[idx];
   T px, py;
@@ -285,12 +390,11 @@ __global__ __launch_bounds__(kBlock) void k_upwind_corr(LevelData<T> L, int bc_v
                                                          T* __restrict__ xout, T* __restrict__ acc) {
   const int n = L.dims.n, nd = L.dims.nd;
   const size_t ncell = size_t(n) * n;
-  const size_t total = ncell * nd * L.dims.G;
-  const size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const size_t gn = idx / ncell, cell = idx - gn * ncell;
-  const int g = int(gn / nd), dir = int(gn - size_t(g) * nd);
-  const int j = int(cell / n), i = int(cell - size_t(j) * n);
+  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (cell >= int(ncell)) return;
+  const int dir = blockIdx.y, g = blockIdx.z;
+  const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
+  const int j = cell / n, i = cell - j * n;
   const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
   const int iu = mu > T(0) ? i - 1 : i + 1;
   const int ju = nu > T(0) ? j - 1 : j + 1;
@@ -325,12 +429,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<
                                                       T* __restrict__ coarse) {
   const int nc = Lc.dims.n, ndc = Lc.dims.nd, nf = Lf.dims.n, naf = Lf.dims.na;
   const size_t nccell = size_t(nc) * nc, nfcell = size_t(nf) * nf;
-  const size_t total = nccell * ndc * Lc.dims.G;
-  const size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const size_t gn = idx / nccell, cell = idx - gn * nccell;
-  const int g = int(gn / ndc), N = int(gn - size_t(g) * ndc);
-  const int J = int(cell / nc), I = int(cell - size_t(J) * nc);
+  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (cell >= int(nccell)) return;
+  const int N = blockIdx.y, g = blockIdx.z;
+  const size_t idx = (size_t(g) * ndc + N) * nccell + cell;
+  const int J = cell / nc, I = cell - J * nc;
   int kids[4], nk = 0;
   if (naf == 1) {
     kids[nk++] = N;
@@ -355,12 +458,11 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelData<T> Lf, int nac,
                                                      T* __restrict__ fine) {
   const int n = Lf.dims.n, nd = Lf.dims.nd;
   const size_t ncell = size_t(n) * n;
-  const size_t total = ncell * nd * Lf.dims.G;
-  const size_t idx = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (idx >= total) return;
-  const size_t gn = idx / ncell, cell = idx - gn * ncell;
-  const int g = int(gn / nd), dir = int(gn - size_t(g) * nd);
-  const int j = int(cell / n), i = int(cell - size_t(j) * n);
+  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  if (cell >= int(ncell)) return;
+  const int dir = blockIdx.y, g = blockIdx.z;
+  const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
+  const int j = cell / n, i = cell - j * n;
   const int nc = n >> 1;
   fine[idx] = coarse[(size_t(g) * (size_t(8) * nac * nac) + parent_dir_dev(dir, Lf.dims.na)) *
                          (size_t(nc) * nc) + size_t(j >> 1) * nc + (i >> 1)];
@@ -466,10 +568,8 @@ hipError_t launch_emission(const LevelDims& d, const T* phi, const T* ss, int nl
 
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
-                     const T* psi, const T* E, int nmomE, const T* kx, const T* ky, T* out,
-                     T* kx_out, T* ky_out, int mode, T sign, const T* rhs, hipStream_t s) {
-  PGArgs<T> a;
-  a.rhs = rhs;
+                     const PGLaunch<T>& o, hipStream_t s) {
+  PGArgs<T> a{};
   a.L = L;
   a.st = st;
   a.alpha_r = T(pp.alpha_r);
@@ -478,33 +578,61 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.aksq = T(pp.alpha_ksq);
   a.beta = T(pp.beta);
   a.bc_vac = pp.bc_vac;
-  a.psi = psi;
-  a.E = E;
-  a.nmomE = nmomE;
-  a.kx_in = kx;
-  a.ky_in = ky;
-  a.out = out;
-  a.kx_out = kx_out;
-  a.ky_out = ky_out;
-  a.mode = mode;
-  a.sign = sign;
-  const int nt = (L.dims.n + kTile - 1) / kTile;
-  a.ntx = nt;
-  dim3 grid(nt * nt, L.dims.nd, L.dims.G);
+  a.psi = o.psi;
+  a.E = o.E;
+  a.nmomE = o.nmomE;
+  a.rhs = o.rhs;
+  a.mode = o.mode;
+  a.sign = o.sign;
+  const int n = L.dims.n;
+  if (!o.kx_in) {
+    // diffusivities of psi first (into kx_out / ky_out, and / or their float copies)
+    if (!o.kx_out) return hipErrorInvalidValue;
+    a.kx_out = o.kx_out;
+    a.ky_out = o.ky_out;
+    a.kx_out_f = o.kx_out_f;
+    a.ky_out_f = o.ky_out_f;
+    const int ow = kStripW - 2 * p;
+    a.ntx = (n + ow - 1) / ow;
+    const dim3 grid(a.ntx * ((n + kStripH - 1) / kStripH), L.dims.nd, L.dims.G);
+    switch (p) {
+      case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_pg_diffusivity<3, T>), grid, dim3(kStripW), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    a.kx_out = a.ky_out = nullptr;
+    a.kx_out_f = a.ky_out_f = nullptr;
+    a.kx_in = o.kx_out;
+    a.ky_in = o.ky_out;
+  } else {
+    a.kx_in = o.kx_in;
+    a.ky_in = o.ky_in;
+  }
+  a.out = o.out;
+  a.out_f = o.out_f;
+  a.partial = o.partial;
+  a.ntx = (n + kStripW - 1) / kStripW;
+  const dim3 grid(a.ntx * ((n + kStripH - 1) / kStripH), L.dims.nd, L.dims.G);
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_pg<1, T>), grid, dim3(kBlock), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pg<2, T>), grid, dim3(kBlock), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pg<3, T>), grid, dim3(kBlock), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_pg_stream<1, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pg_stream<2, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pg_stream<3, T>), grid, dim3(kStripW), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }
 
+size_t pg_partials(const LevelDims& d) {
+  const size_t strips = size_t((d.n + kStripW - 1) / kStripW) * ((d.n + kStripH - 1) / kStripH);
+  return strips * d.nd * d.G;
+}
+
 template <typename T>
 hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, const T* E, int nmomE,
                               T* out, int mode, T sign, const T* rhs, hipStream_t s) {
-  const size_t total = size_t(L.dims.n) * L.dims.n * L.dims.nd * L.dims.G;
-  hipLaunchKernelGGL(k_upwind_full<T>, dim3(nblocks(total)), dim3(kBlock), 0, s, L, bc_vac, psi, E,
+  const dim3 grid(nblocks(size_t(L.dims.n) * L.dims.n), L.dims.nd, L.dims.G);
+  hipLaunchKernelGGL(k_upwind_full<T>, grid, dim3(kBlock), 0, s, L, bc_vac, psi, E,
                      nmomE, out, mode, sign, rhs);
   return hipGetLastError();
 }
@@ -512,8 +640,7 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
                                     int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s) {
-  const size_t total = size_t(L.dims.n) * L.dims.n * L.dims.nd * L.dims.G;
-  const dim3 grid(nblocks(total)), blk(kBlock);
+  const dim3 grid(nblocks(size_t(L.dims.n) * L.dims.n), L.dims.nd, L.dims.G), blk(kBlock);
   if (xmode == 0)
     hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
   else if (xmode == 1)
@@ -526,15 +653,15 @@ hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* 
 template <typename T>
 hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine, T* coarse,
                            hipStream_t s) {
-  const size_t total = size_t(Lc.dims.n) * Lc.dims.n * Lc.dims.nd * Lc.dims.G;
-  hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(total)), dim3(kBlock), 0, s, Lf, Lc, fine, coarse);
+  const dim3 grid(nblocks(size_t(Lc.dims.n) * Lc.dims.n), Lc.dims.nd, Lc.dims.G);
+  hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, s, Lf, Lc, fine, coarse);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(const LevelData<T>& Lf, int nac, const T* coarse, T* fine, hipStream_t s) {
-  const size_t total = size_t(Lf.dims.n) * Lf.dims.n * Lf.dims.nd * Lf.dims.G;
-  hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(total)), dim3(kBlock), 0, s, Lf, nac, coarse, fine);
+  const dim3 grid(nblocks(size_t(Lf.dims.n) * Lf.dims.n), Lf.dims.nd, Lf.dims.G);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, Lf, nac, coarse, fine);
   return hipGetLastError();
 }
 
@@ -545,6 +672,11 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
                          double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_wnorm2_partial<T>, dim3(npartial), dim3(kBlock), 0, s, L, v, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, npartial, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, np, out);
   return hipGetLastError();
 }
 
@@ -578,8 +710,7 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s) {
   template hipError_t launch_emission<T>(const LevelDims&, const T*, const T*, int, const T*, T*,   \
                                          hipStream_t);                                              \
   template hipError_t launch_pg<T>(int, const LevelData<T>&, const Stencils<T>&, const PGParams&,   \
-                                   const T*, const T*, int, const T*, const T*, T*, T*, T*, int, T, \
-                                   const T*, hipStream_t);                                          \
+                                   const PGLaunch<T>&, hipStream_t);                                \
   template hipError_t launch_upwind_full<T>(const LevelData<T>&, int, const T*, const T*, int, T*,  \
                                             int, T, const T*, hipStream_t);                         \
   template hipError_t launch_upwind_correction<T>(const LevelData<T>&, int, const T*, int, int,     \
