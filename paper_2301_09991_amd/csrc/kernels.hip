@@ -37,30 +37,62 @@ __device__ __forceinline__ bool halo_zero(int gi, int gj, int n, T mu, T nu, int
 }
 
 // ---------------------------------------------------------------------------------------------
-// moments: phi[g][m][cell] = sum_n w_n Y_m(n) psi[g][n][cell], Y = (1, mu, nu)
+// moments: phi[g][m][cell] = sum_n w_n Y_m(n) psi[g][n][cell], Y = (1, mu, nu).
+// A block covers 64 cells; its four waves each sum a contiguous quarter of the ordinates
+// (four loads in flight per lane), and the quarters are added in a fixed order.
+constexpr int kMomCells = 64;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __restrict__ psi,
                                                      T* __restrict__ phi, int nmom) {
-  const size_t ncell = size_t(L.dims.n) * L.dims.n;
-  const size_t t = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  const int ncell = L.dims.n * L.dims.n;
+  const int lane = threadIdx.x % kMomCells, q = threadIdx.x / kMomCells;
+  const int cell = blockIdx.x * kMomCells + lane;
   const int g = blockIdx.y;
-  if (t >= ncell) return;
-  const T* src = psi + size_t(g) * L.dims.nd * ncell + t;
+  const int nd = L.dims.nd, per = nd / 4;
+  __shared__ T red[3][4][kMomCells];
   T a0 = 0, a1 = 0, a2 = 0;
-  for (int d = 0; d < L.dims.nd; ++d) {
-    const T v = src[size_t(d) * ncell];
-    const T w = L.w[d];
-    a0 += w * v;
-    if (nmom > 1) {
-      a1 += (w * L.mu[d]) * v;
-      a2 += (w * L.nu[d]) * v;
+  if (cell < ncell) {
+    const T* src = psi + (size_t(g) * nd + size_t(q) * per) * ncell + cell;
+    const T* w = L.w + q * per;
+    const T* mu = L.mu + q * per;
+    const T* nu = L.nu + q * per;
+    int d = 0;
+    for (; d + 4 <= per; d += 4) {
+      const T v0 = src[size_t(d) * ncell], v1 = src[size_t(d + 1) * ncell];
+      const T v2 = src[size_t(d + 2) * ncell], v3 = src[size_t(d + 3) * ncell];
+      a0 += w[d] * v0;
+      a0 += w[d + 1] * v1;
+      a0 += w[d + 2] * v2;
+      a0 += w[d + 3] * v3;
+      if (nmom > 1) {
+        a1 += (w[d] * mu[d]) * v0;
+        a1 += (w[d + 1] * mu[d + 1]) * v1;
+        a1 += (w[d + 2] * mu[d + 2]) * v2;
+        a1 += (w[d + 3] * mu[d + 3]) * v3;
+        a2 += (w[d] * nu[d]) * v0;
+        a2 += (w[d + 1] * nu[d + 1]) * v1;
+        a2 += (w[d + 2] * nu[d + 2]) * v2;
+        a2 += (w[d + 3] * nu[d + 3]) * v3;
+      }
+    }
+    for (; d < per; ++d) {
+      const T v = src[size_t(d) * ncell];
+      a0 += w[d] * v;
+      if (nmom > 1) {
+        a1 += (w[d] * mu[d]) * v;
+        a2 += (w[d] * nu[d]) * v;
+      }
     }
   }
-  T* dst = phi + size_t(g) * nmom * ncell + t;
-  dst[0] = a0;
-  if (nmom > 1) {
-    dst[ncell] = a1;
-    dst[2 * ncell] = a2;
+  red[0][q][lane] = a0;
+  red[1][q][lane] = a1;
+  red[2][q][lane] = a2;
+  __syncthreads();
+  if (q == 0 && cell < ncell) {
+    T* dst = phi + size_t(g) * nmom * ncell + cell;
+    for (int m = 0; m < nmom; ++m)
+      dst[size_t(m) * ncell] = (red[m][0][lane] + red[m][1][lane]) + (red[m][2][lane] + red[m][3][lane]);
   }
 }
 
@@ -180,18 +212,32 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   const int yend = min(y0 + kStripH, n);
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
-  for (int r = y0 - P; r < yend + P; ++r) {
+  // row values are loaded one row ahead so that the loads overlap the filtering of a row
+  T p0, k0, q0, p1 = 0, k1 = 0, q1 = 0;
+  auto load_row = [&](int r, T& vp0, T& vk0, T& vq0, T& vp1, T& vk1, T& vq1) {
     const int cr = clampi(r, 0, n - 1);
     const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
     const size_t ro = size_t(cr) * n;
-    s_psi[lane] = (zy || zx0) ? T(0) : psi[ro + cc0];
-    s_kx[lane] = kxin[ro + cc0];
-    s_ky[lane] = kyin[ro + cc0];
+    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
+    vk0 = kxin[ro + cc0];
+    vq0 = kyin[ro + cc0];
     if (lane < 2 * P) {
-      s_psi[kStripW + lane] = (zy || zx1) ? T(0) : psi[ro + cc1];
-      s_kx[kStripW + lane] = kxin[ro + cc1];
-      s_ky[kStripW + lane] = kyin[ro + cc1];
+      vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+      vk1 = kxin[ro + cc1];
+      vq1 = kyin[ro + cc1];
     }
+  };
+  load_row(y0 - P, p0, k0, q0, p1, k1, q1);
+  for (int r = y0 - P; r < yend + P; ++r) {
+    s_psi[lane] = p0;
+    s_kx[lane] = k0;
+    s_ky[lane] = q0;
+    if (lane < 2 * P) {
+      s_psi[kStripW + lane] = p1;
+      s_kx[kStripW + lane] = k1;
+      s_ky[kStripW + lane] = q1;
+    }
+    if (r + 1 < yend + P) load_row(r + 1, p0, k0, q0, p1, k1, q1);
     __syncthreads();
     T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
 #pragma unroll
@@ -293,12 +339,19 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   const bool writer = lane >= P && lane < kStripW - P && gi < n && gi < xs + OW;
   const int yend = min(y0 + kStripH, n);
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
-  for (int r = y0 - 2 * P; r < yend + 2 * P; ++r) {
+  T p0, p1 = 0;
+  auto load_row = [&](int r, T& vp0, T& vp1) {
     const int cr = clampi(r, 0, n - 1);
     const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
     const size_t ro = size_t(cr) * n;
-    s_psi[lane] = (zy || zx0) ? T(0) : psi[ro + cc0];
-    if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : psi[ro + cc1];
+    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
+    if (lane < 2 * P) vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+  };
+  load_row(y0 - 2 * P, p0, p1);
+  for (int r = y0 - 2 * P; r < yend + 2 * P; ++r) {
+    s_psi[lane] = p0;
+    if (lane < 2 * P) s_psi[kStripW + lane] = p1;
+    if (r + 1 < yend + 2 * P) load_row(r + 1, p0, p1);
     __syncthreads();
     T xd = 0, xm = 0;
 #pragma unroll
@@ -551,9 +604,9 @@ inline unsigned nblocks(size_t total) { return unsigned((total + kBlock - 1) / k
 // ---------------------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_moments(const LevelData<T>& L, const T* psi, T* phi, int nmom, hipStream_t s) {
-  const size_t ncell = size_t(L.dims.n) * L.dims.n;
-  hipLaunchKernelGGL(k_moments<T>, dim3(nblocks(ncell), L.dims.G), dim3(kBlock), 0, s, L, psi, phi,
-                     nmom);
+  const int ncell = L.dims.n * L.dims.n;
+  hipLaunchKernelGGL(k_moments<T>, dim3((ncell + kMomCells - 1) / kMomCells, L.dims.G), dim3(kBlock),
+                     0, s, L, psi, phi, nmom);
   return hipGetLastError();
 }
 
