@@ -152,6 +152,12 @@ int ctf_apply_operator(ctf_problem* prob, const double* psi, double* out, int mo
  * (section "Discrete Ordinates": phi_g = sum p_n psi_n).  phi: device float64 [G][3][N][N]. */
 int ctf_moments(ctf_problem* prob, const double* psi, double* phi);
 
+/* Float32 moments of a float32 angular flux (mixed-precision problems only): phi device float32
+ * [G][3][N][N].  use_mfma = 1 evaluates the contraction on bf16 MFMA with float32 accumulation
+ * (psi rounded to bf16, weights kept as a bf16 hi + lo pair); 0 uses float32 vector arithmetic.
+ * The inner cycles of CTF_FP32_IR_BF16_MOMENTS use the MFMA form. */
+int ctf_moments_f32(ctf_problem* prob, const float* psi, float* phi, int use_mfma);
+
 /* Compute and hold the PG diffusivities k_x, k_y of psi (eq. ano-k) for the frozen-k
  * discretisation; if kx / ky are non-NULL they also receive a device float64 copy
  * [G][n_dir][N][N]. */
@@ -201,6 +207,7 @@ enum {
   CTF_T_MOMENTS,
   CTF_T_EMISSION,
   CTF_T_NORM,
+  CTF_T_MOMENTS_MFMA,  /* bf16 MFMA moment contraction */
   CTF_T_COUNT
 };
 int ctf_timing_enable(ctf_problem* prob, int on, int capacity);

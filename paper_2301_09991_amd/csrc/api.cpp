@@ -113,6 +113,7 @@ struct ctf_problem {
   float* e_f = nullptr;    // float32 correction of a refinement step
   float* e_tmp_f = nullptr;
   float* r_f = nullptr;    // float32 right-hand side of the correction equation
+  float* psi32_f = nullptr;  // psi64 rounded (full-approximation refinement)
   double* partial = nullptr;
   double* scal = nullptr;  // device scalars
   int npartial = 0;
@@ -209,6 +210,7 @@ size_t layout(ctf_problem* P, char* base) {
     P->e_f = c.take<float>(P->dof(0));
     P->e_tmp_f = c.take<float>(P->dof(0));
     P->r_f = c.take<float>(P->dof(0));
+    P->psi32_f = cfg.discretisation == CTF_CONVFEM_PG ? c.take<float>(P->dof(0)) : nullptr;
   }
   P->npartial = wnorm2_partials(P->dims[0]);
   P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0])));
@@ -373,15 +375,26 @@ int cycle_rest64(ctf_problem* P, double* psi) {
   return CTF_OK;
 }
 
-// ---- mixed precision: one float32 cycle on the correction equation A_k e = r --------------------
-// r (float32, P->r_f) is the float64 residual rounded; k is frozen at the outer psi (float32 in
-// kx_f, ky_f); e in P->e_f.
-int inner_finest32(ctf_problem* P, const float* e, float* out, int mode) {
+// ---- mixed precision ------------------------------------------------------------------------------
+// Linear discretisations (upwind, frozen k): float32 cycles on the correction equation A e = r,
+// r the float64 residual rounded to float32 (P->r_f), e in P->e_f, starting from e = 0.
+// Non-linear Petrov-Galerkin: full-approximation form.  With psi32 = psi64 rounded, the float32
+// cycles solve A32(u) = b32, b32 = A32(psi32) + rho64, from u = psi32 (k recomputed from u in
+// every float32 residual, as the float64 cycle does), and psi64 += u - psi32.  In both forms the
+// float32 fixed point is the float64 one up to float32 rounding, which the float64 refinement
+// removes.
+
+// float32 finest operator on x (emission of x without source, per-DOF term r_f):
+//   mode 0: out = sign (r_f + q(x) - L x);  mode 1: out = x + (r_f + q(x) - L x)/(beta d)
+int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float sign = 1.0f) {
   const ctf_config& c = P->cfg;
   const int nl = c.scatter_order + 1;
-  {
+  if (c.precision == CTF_FP32_IR_BF16_MOMENTS) {
+    Timed t(P, CTF_T_MOMENTS_MFMA);
+    CTF_HIP(launch_moments_mfma(P->lf(0), x, P->phi_f, P->nmom, P->stream));
+  } else {
     Timed t(P, CTF_T_MOMENTS);
-    CTF_HIP(launch_moments<float>(P->lf(0), e, P->phi_f, P->nmom, P->stream));
+    CTF_HIP(launch_moments<float>(P->lf(0), x, P->phi_f, P->nmom, P->stream));
   }
   {
     Timed t(P, CTF_T_EMISSION);
@@ -389,24 +402,31 @@ int inner_finest32(ctf_problem* P, const float* e, float* out, int mode) {
   }
   if (c.discretisation == CTF_UPWIND) {
     Timed t(P, CTF_T_UPWIND32);
-    CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, e, P->E_f, P->nmom, out, mode, 1.0f,
+    CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, x, P->E_f, P->nmom, out, mode, sign,
                                       P->r_f, P->stream));
     return CTF_OK;
   }
   PGLaunch<float> o;
-  o.psi = e;
+  o.psi = x;
   o.E = P->E_f;
   o.nmomE = P->nmom;
-  o.kx_in = P->kx_f;
-  o.ky_in = P->ky_f;
+  if (c.discretisation == CTF_CONVFEM_PG && x != P->psi32_f) {
+    o.kx_out = P->kx_f;  // full-approximation form: diffusivities of the iterate itself
+    o.ky_out = P->ky_f;
+  } else {
+    o.kx_in = P->kx_f;   // frozen k, or the k of psi64 for b32 = A32(psi32) + rho64
+    o.ky_in = P->ky_f;
+  }
   o.out = out;
   o.rhs = P->r_f;
   o.mode = mode;
+  o.sign = sign;
   Timed t(P, CTF_T_PG32);
   CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, o, P->stream));
   return CTF_OK;
 }
 
+// one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0)
 int inner_cycle32(ctf_problem* P, bool e_is_zero) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
@@ -444,9 +464,8 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero) {
   return CTF_OK;
 }
 
-// float64 residual of psi, rounded to float32 into r_f (and kept in float64 in rho[0] for the
-// upwind / frozen-k discretisations); the diffusivities of psi go to kx_f, ky_f for the inner
-// float32 cycles.  Returns ||rho||_W / ||b||_W through rel.
+// Float64 residual of psi and its norm.  r_f receives rho64 rounded to float32 (linear forms) or
+// -rho64 (full-approximation form, see refine_rest).  Returns ||rho||_W / ||b||_W through rel.
 int outer_residual(ctf_problem* P, const double* psi, double* rel) {
   int rc = emission64(P, psi, true);
   if (rc) return rc;
@@ -454,7 +473,7 @@ int outer_residual(ctf_problem* P, const double* psi, double* rel) {
   const size_t n = P->dof(0);
   double nr = 0.0;
   if (disc == CTF_CONVFEM_PG) {
-    rc = finest64(P, psi, nullptr, 0, 1.0, P->r_f, true, true);
+    rc = finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, true);
     if (rc) return rc;
     rc = read_norm(P, &nr);
   } else {
@@ -474,12 +493,25 @@ int outer_residual(ctf_problem* P, const double* psi, double* rel) {
 
 // one refinement step after outer_residual: n_inner float32 cycles and the float64 update
 int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done) {
-  int it = 0;
-  for (; it < P->cfg.n_inner && it < max_inner; ++it) {
-    int rc = inner_cycle32(P, it == 0);
+  const size_t n = P->dof(0);
+  const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
+  if (fas) {
+    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64), with
+    // the diffusivities of psi64 left in kx_f, ky_f by the float64 residual
+    CTF_HIP(launch_convert_d2f(psi, P->psi32_f, n, P->stream));
+    CTF_HIP(hipMemcpyAsync(P->e_f, P->psi32_f, n * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+    int rc = inner_finest32(P, P->psi32_f, P->r_f, 0, -1.0f);
     if (rc) return rc;
   }
-  if (it > 0) CTF_HIP(launch_add_f2d(psi, P->e_f, P->dof(0), P->stream));
+  int it = 0;
+  for (; it < P->cfg.n_inner && it < max_inner; ++it) {
+    int rc = inner_cycle32(P, !fas && it == 0);
+    if (rc) return rc;
+  }
+  if (it > 0) {
+    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, P->psi32_f, n, P->stream));
+    else CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
+  }
   if (done) *done = it;
   return CTF_OK;
 }
@@ -688,6 +720,19 @@ int ctf_apply_operator(ctf_problem* P, const double* psi, double* out, int mode)
 int ctf_moments(ctf_problem* P, const double* psi, double* phi) {
   if (!P || !psi || !phi) return fail(CTF_EINVAL, "null argument");
   CTF_HIP(launch_moments<double>(P->ld(0), psi, phi, 3, P->stream));
+  return CTF_OK;
+}
+
+int ctf_moments_f32(ctf_problem* P, const float* psi, float* phi, int use_mfma) {
+  if (!P || !psi || !phi) return fail(CTF_EINVAL, "null argument");
+  if (!P->mixed()) return fail(CTF_EINVAL, "float32 moments need a mixed-precision problem");
+  if (use_mfma) {
+    Timed t(P, CTF_T_MOMENTS_MFMA);
+    CTF_HIP(launch_moments_mfma(P->lf(0), psi, phi, 3, P->stream));
+  } else {
+    Timed t(P, CTF_T_MOMENTS);
+    CTF_HIP(launch_moments<float>(P->lf(0), psi, phi, 3, P->stream));
+  }
   return CTF_OK;
 }
 

@@ -73,6 +73,10 @@ struct PGParams {
 template <typename T>
 hipError_t launch_moments(const LevelData<T>& L, const T* psi, T* phi, int nmom, hipStream_t s);
 
+// The same contraction on bf16 MFMA (float32 accumulation), for float32 psi.
+hipError_t launch_moments_mfma(const LevelData<float>& L, const float* psi, float* phi, int nmom,
+                               hipStream_t s);
+
 // E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2 (E1, E2 only if nl == 2), divided by 4 pi;
 // source == null: no external source.
 template <typename T>
@@ -146,5 +150,7 @@ hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s);
 // y(double) += x(float)
 hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s);
+// y(double) += u(float) - v(float)
+hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s);
 
 }  // namespace ctf

@@ -96,6 +96,81 @@ __global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __r
   }
 }
 
+// BF16 MFMA form of the moment contraction (float32 psi in memory):
+//   Phi[m][cell] = sum_n W[m][n] psi[n][cell],  W = (w, w mu, w nu),
+// as a [16 x n_dir] x [n_dir x cells] product on v_mfma_f32_16x16x16_bf16 with float32
+// accumulation (rows 3..15 of W are zero).  psi is rounded to bf16 once; the weights are
+// carried as a bf16 pair (hi + lo, two MFMAs per K-chunk) so that they keep ~16 bits.
+// A block owns 64 cells (four 16-cell MFMA tiles); its four waves each take a quarter of the
+// ordinates, and the quarters are summed in a fixed order through LDS.
+typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ unsigned short bf16_rne(float x) {
+  unsigned int u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<unsigned short>(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_float(unsigned short b) {
+  return __uint_as_float(static_cast<unsigned int>(b) << 16);
+}
+
+__global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, const float* __restrict__ psi,
+                                                          float* __restrict__ phi, int nmom) {
+  const int ncell = L.dims.n * L.dims.n;
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+  const int c0 = blockIdx.x * 64;
+  const int g = blockIdx.y;
+  const int nd = L.dims.nd;
+  const int per = nd / 4;                     // ordinates of this wave (a multiple of 2 at least)
+  const int i = lane % 16, kq = lane / 16;    // A row / B column, and the K quarter of the lane
+  v4f_t acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
+  const float* base = psi + size_t(g) * nd * ncell;
+  for (int n0 = wave * per; n0 < (wave + 1) * per; n0 += 16) {
+    v4s_t ahi, alo;
+    v4s_t b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + 4 * kq + j;
+      const bool inK = n < (wave + 1) * per;
+      float wv = 0.f;
+      if (inK && i < 3) wv = L.w[n] * (i == 0 ? 1.f : (i == 1 ? L.mu[n] : L.nu[n]));
+      const unsigned short hi = bf16_rne(wv);
+      ahi[j] = static_cast<short>(hi);
+      alo[j] = static_cast<short>(bf16_rne(wv - bf16_to_float(hi)));
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int c = c0 + 16 * t + i;
+        const float v = (inK && c < ncell) ? base[size_t(n) * ncell + c] : 0.f;
+        b[t][j] = static_cast<short>(bf16_rne(v));
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, b[t], acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, b[t], acc[t], 0, 0, 0);
+    }
+  }
+  // D layout: lane holds rows 4*(lane/16) .. +3 of column lane % 16; rows 0..2 are the moments
+  __shared__ float red[4][3][64];
+  if (kq == 0) {
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) red[wave][m][16 * t + i] = acc[t][m];
+  }
+  __syncthreads();
+  if (wave == 0) {
+    const int c = c0 + lane;
+    if (c < ncell)
+      for (int m = 0; m < nmom; ++m)
+        phi[(size_t(g) * nmom + m) * ncell + c] =
+            (red[0][m][lane] + red[1][m][lane]) + (red[2][m][lane] + red[3][m][lane]);
+  }
+}
+
 // emission E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2, all divided by 4 pi
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __restrict__ phi,
@@ -345,7 +420,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
     const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
     const size_t ro = size_t(cr) * n;
     vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
-    if (lane < 2 * P) vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+    if (lane < 2 * P) {
+      vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+    }
   };
   load_row(y0 - 2 * P, p0, p1);
   for (int r = y0 - 2 * P; r < yend + 2 * P; ++r) {
@@ -597,6 +674,12 @@ __global__ __launch_bounds__(kBlock) void k_add_f2d(double* __restrict__ y, cons
   if (i < n) y[i] += double(x[i]);
 }
 
+__global__ __launch_bounds__(kBlock) void k_add_diff_f2d(double* __restrict__ y, const float* __restrict__ u,
+                                                          const float* __restrict__ v, size_t n) {
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) y[i] += double(u[i]) - double(v[i]);
+}
+
 inline unsigned nblocks(size_t total) { return unsigned((total + kBlock - 1) / kBlock); }
 
 }  // namespace
@@ -607,6 +690,14 @@ hipError_t launch_moments(const LevelData<T>& L, const T* psi, T* phi, int nmom,
   const int ncell = L.dims.n * L.dims.n;
   hipLaunchKernelGGL(k_moments<T>, dim3((ncell + kMomCells - 1) / kMomCells, L.dims.G), dim3(kBlock),
                      0, s, L, psi, phi, nmom);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments_mfma(const LevelData<float>& L, const float* psi, float* phi, int nmom,
+                               hipStream_t s) {
+  const int ncell = L.dims.n * L.dims.n;
+  hipLaunchKernelGGL(k_moments_mfma, dim3((ncell + 63) / 64, L.dims.G), dim3(kBlock), 0, s, L, psi,
+                     phi, nmom);
   return hipGetLastError();
 }
 
@@ -751,6 +842,10 @@ hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_
 }
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n);
+  return hipGetLastError();
+}
+hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, v, n);
   return hipGetLastError();
 }
 hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s) {

@@ -23,10 +23,10 @@ EXPORTED = [
     "ctf_num_levels", "ctf_level_info", "ctf_level_quadrature", "ctf_convfem_stencils",
     "ctf_level_sigma_t", "ctf_apply_operator", "ctf_moments", "ctf_freeze_k", "ctf_smooth",
     "ctf_restrict", "ctf_prolong", "ctf_mg_cycle", "ctf_solve", "ctf_norm", "ctf_last_error",
-    "ctf_quadrature", "ctf_timing_enable", "ctf_timing_read",
+    "ctf_quadrature", "ctf_timing_enable", "ctf_timing_read", "ctf_moments_f32",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
-                 "emission", "norm"]
+                 "emission", "norm", "moments_mfma"]
 
 
 class Config(ctypes.Structure):
@@ -60,6 +60,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"HIP library {LIB_PATH} is not built: run paper_2301_09991_amd/build.py")
+    # PyTorch first: libctf.so then binds to the HIP runtime PyTorch loaded (same soname), so
+    # device pointers and streams handed over from torch tensors are valid in the library.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, D, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
     cfgp = ctypes.POINTER(Config)
@@ -76,6 +79,7 @@ def load():
         "ctf_level_sigma_t": (I, [P, I, P]),
         "ctf_apply_operator": (I, [P, P, P, I]),
         "ctf_moments": (I, [P, P, P]),
+        "ctf_moments_f32": (I, [P, P, P, I]),
         "ctf_freeze_k": (I, [P, P, P, P]),
         "ctf_smooth": (I, [P, I, I, P, P, I]),
         "ctf_restrict": (I, [P, I, P, P]),
@@ -217,6 +221,10 @@ class Problem:
     def moments(self, psi, phi):
         _check(self.lib.ctf_moments(self.handle, _ptr(psi), _ptr(phi)))
         return phi
+
+    def moments_f32(self, psi32, phi32, use_mfma=True):
+        _check(self.lib.ctf_moments_f32(self.handle, _ptr(psi32), _ptr(phi32), int(use_mfma)))
+        return phi32
 
     def freeze_k(self, psi, kx=None, ky=None):
         _check(self.lib.ctf_freeze_k(self.handle, _ptr(psi), _ptr(kx), _ptr(ky)))
