@@ -73,6 +73,9 @@ typedef struct ctf_config {
   double alpha_r;      /* factor of the anisotropic residual estimates (paper: 3) */
   double eps_k;        /* epsilon_k of the diffusivities (paper: 0.001) */
   int n_inner;         /* float32 cycles per float64 refinement step (precision != FP64) */
+  int cnn_level;       /* level of the learned coarse-grid correction, -1 = none (one group only) */
+  double cnn_max_growth; /* the correction is switched off once a cycle applying it multiplies the
+                            residual by more than this (default 1: it must not grow) */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;
@@ -92,10 +95,12 @@ typedef struct ctf_solve_info {
   double seconds;          /* wall time of the call */
   double* history;         /* optional caller buffer of history_len doubles: residual per check */
   int history_len;
+  int cnn_applied;         /* cycles that applied the learned correction */
+  int cnn_rejected;        /* 1 if the learned correction raised the residual and was switched off */
 } ctf_solve_info;
 
 /* Fill cfg with the paper's defaults: p = 1, na = 4, vacuum boundaries, upwind sweeps n_j = 2,
- * n_pg = 2, beta_pg = 3, alpha_r = 3, eps_k = 1e-3, FP64, n_inner = 2. */
+ * n_pg = 2, beta_pg = 3, alpha_r = 3, eps_k = 1e-3, FP64, n_inner = 2, no learned correction. */
 void ctf_default_config(ctf_config* cfg);
 
 /* Bytes of device workspace a problem with this configuration needs (0 on invalid cfg; the
@@ -191,6 +196,45 @@ int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_s
 /* ||v||_W of a finest-level array (synchronous). */
 int ctf_norm(ctf_problem* prob, const double* v, double* out);
 
+/* ---- learned coarse-grid correction ---------------------------------------------------------
+ * Not in the paper (its filters are fixed); this project's own extension.  A four-layer 3x3
+ * convolutional network (channels 3 -> 32 -> 32 -> 32 -> 1, ReLU after the first three, zero
+ * padding) maps three fields on the grid of level cnn_level -- the angle-integrated restricted
+ * residual sum_n w_n rho_n divided by its RMS s, H sigma_t, and the mean scattering ratio -- to the
+ * angle-integrated error left by a plain sawtooth cycle, in units of s.  In a cycle with the
+ * correction, psi (or the float32 correction) gains s * net / (4 pi) in every ordinate, copied to
+ * the fine cells, after the finest correction sweeps and before the finest smoothing.  In
+ * ctf_solve plain multigrid stays the judge: a step with the correction that multiplies the
+ * residual by more than cnn_max_growth (or makes it non-finite) is undone and the correction is
+ * switched off for the rest of the solve.
+ * Parameters: float32 device vector of ctf_cnn_param_count() values, W1 b1 W2 b2 W3 b3 W4 b4 with
+ * W[c_out][c_in][ky][kx].  Activations: float32 [batch][channel][y][x]. */
+int ctf_cnn_param_count(void);
+/* Device workspace for ctf_cnn_forward / ctf_cnn_loss_grad at this batch and size. */
+size_t ctf_cnn_workspace_bytes(int batch, int h, int w);
+/* out[batch][1][h][w] = net(in[batch][3][h][w]).  bf16 = 1: activations rounded to bf16 and
+ * the convolutions on bf16 MFMA with float32 accumulation; 0: float32 vector arithmetic. */
+int ctf_cnn_forward(const float* params, const float* in, float* out, int batch, int h, int w, int bf16,
+                    void* workspace, size_t ws_bytes, void* stream);
+/* Mean-squared-error loss of net(in) against target[batch][1][h][w] (loss: device float64 scalar)
+ * and its gradient grad (device float32, ctf_cnn_param_count() values). */
+int ctf_cnn_loss_grad(const float* params, const float* in, const float* target, int batch, int h,
+                      int w, int bf16, float* grad, double* loss, void* workspace, size_t ws_bytes,
+                      void* stream);
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) at step >= 1 on params with moments m, v. */
+int ctf_cnn_adam(float* params, float* m, float* v, const float* grad, int n, int step, float lr,
+                 void* stream);
+/* Copy the network parameters into a problem created with cnn_level >= 0 and switch it on. */
+int ctf_cnn_attach(ctf_problem* prob, const float* params);
+/* Switch an attached network on (1) or off (0). */
+int ctf_cnn_enable(ctf_problem* prob, int on);
+/* Training sample (float64 problems): one plain sawtooth cycle in place on psi; features receives
+ * the network input of the cycle's starting residual (device float32 [3][n_c][n_c] on the grid of
+ * cnn_level), target the angle-integrated error psi_star - psi after the cycle averaged onto that
+ * grid and divided by the feature scale s, and *scale (host) receives s. */
+int ctf_cnn_sample(ctf_problem* prob, double* psi, const double* psi_star, float* features,
+                   float* target, double* scale);
+
 /* In-library kernel timers (HIP events recorded on the problem's stream around each launch of a
  * kernel class).  ctf_timing_enable(prob, 1, cap) synchronises, clears the counters and records
  * at most cap launches per class from then on; (prob, 0, 0) stops recording.
@@ -208,6 +252,7 @@ enum {
   CTF_T_EMISSION,
   CTF_T_NORM,
   CTF_T_MOMENTS_MFMA,  /* bf16 MFMA moment contraction */
+  CTF_T_CNN,           /* learned correction: features, network, application */
   CTF_T_COUNT
 };
 int ctf_timing_enable(ctf_problem* prob, int on, int capacity);

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libctf.so")
-SOURCES = ["api.cpp", "setup.cpp", "kernels.hip"]
+SOURCES = ["api.cpp", "setup.cpp", "kernels.hip", "cnn.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed float32 instructions stay off (-packed-fp32-ops): plain float code only.

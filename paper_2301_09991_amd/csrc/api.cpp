@@ -51,6 +51,9 @@ int validate(const ctf_config* c) {
   if (c->max_levels < 0 || c->max_levels > kMaxLevels) return fail(CTF_EINVAL, "bad max_levels");
   if (c->precision != CTF_FP64 && c->n_inner < 1) return fail(CTF_EINVAL, "n_inner >= 1");
   if (!(c->beta_pg > 0.0) || !(c->eps_k > 0.0)) return fail(CTF_EINVAL, "beta_pg, eps_k > 0");
+  if (c->cnn_level >= 0 && !(c->cnn_max_growth > 0.0)) return fail(CTF_EINVAL, "cnn_max_growth > 0");
+  if (c->cnn_level >= 0 && c->ngroups != 1)
+    return fail(CTF_EUNSUPPORTED, "the learned correction supports one energy group");
   return CTF_OK;
 }
 
@@ -122,6 +125,17 @@ struct ctf_problem {
   Stencils<float> st_f{};
   PGParams pp{};
   int bc_vac = 0;
+  // learned coarse-grid correction
+  int cnn_level = -1;
+  bool cnn_on = false;
+  bool cnn_ready = false;
+  float* cnn_params = nullptr;
+  float* cnn_feat = nullptr;   // [3][nc][nc]
+  float* cnn_out = nullptr;    // [nc][nc]
+  void* cnn_ws = nullptr;
+  size_t cnn_ws_bytes = 0;
+  double* cnn_scale = nullptr;
+  double* cnn_backup = nullptr;  // psi before a step with the correction (restored on rejection)
   // in-library kernel timers: per kernel class, pairs of events recorded around each launch
   bool timing = false;
   int timing_cap = 0;
@@ -211,6 +225,16 @@ size_t layout(ctf_problem* P, char* base) {
     P->e_tmp_f = c.take<float>(P->dof(0));
     P->r_f = c.take<float>(P->dof(0));
     P->psi32_f = cfg.discretisation == CTF_CONVFEM_PG ? c.take<float>(P->dof(0)) : nullptr;
+  }
+  if (cfg.cnn_level >= 0 && cfg.cnn_level < P->L) {
+    const int nc = P->dims[cfg.cnn_level].n;
+    P->cnn_params = c.take<float>(cnn_param_count());
+    P->cnn_feat = c.take<float>(3 * size_t(nc) * nc);
+    P->cnn_out = c.take<float>(size_t(nc) * nc);
+    P->cnn_ws_bytes = cnn_workspace_bytes(1, nc, nc);
+    P->cnn_ws = c.take<char>(P->cnn_ws_bytes);
+    P->cnn_scale = c.take<double>(4);
+    P->cnn_backup = c.take<double>(P->dof(0));
   }
   P->npartial = wnorm2_partials(P->dims[0]);
   P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0])));
@@ -345,13 +369,31 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
   return CTF_OK;
 }
 
-// the part of the sawtooth cycle after rho_0 (in P->rho[0]) is known
-int cycle_rest64(ctf_problem* P, double* psi) {
+// network input from the restricted residual on the correction level (cnn_feat[0], cnn_scale);
+// with run_net, also the network output (cnn_out)
+template <typename T>
+int cnn_features_and_net(ctf_problem* P, const LevelData<T>& Lc, const T* rho_c, bool run_net) {
+  Timed t(P, CTF_T_CNN);
+  CTF_HIP(cnn_scalar_residual<T>(Lc, rho_c, P->cnn_feat, P->cnn_scale, P->stream));
+  if (run_net) {
+    const int nc = Lc.dims.n;
+    CTF_HIP(cnn_forward(P->cnn_params, P->cnn_feat, P->cnn_out, 1, nc, nc, 1, P->cnn_ws, P->stream));
+  }
+  return CTF_OK;
+}
+
+// the part of the sawtooth cycle after rho_0 (in P->rho[0]) is known; use_cnn: apply the learned
+// correction; features_only: compute the network input but do not apply the network
+int cycle_rest64(ctf_problem* P, double* psi, bool use_cnn = false, bool features_only = false) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
   for (int l = 1; l < L; ++l) {
     Timed t(P, CTF_T_RESTRICT);
     CTF_HIP(launch_restrict<double>(P->ld(l - 1), P->ld(l), P->rho[l - 1], P->rho[l], P->stream));
+  }
+  if (use_cnn || features_only) {
+    int rc = cnn_features_and_net<double>(P, P->ld(P->cnn_level), P->rho[P->cnn_level], use_cnn);
+    if (rc) return rc;
   }
   const double* e = nullptr;
   for (int l = L - 1; l >= 0; --l) {
@@ -359,6 +401,11 @@ int cycle_rest64(ctf_problem* P, double* psi) {
     int rc = correction_sweeps<double>(P, P->ld(l), l, e, xmode, P->rho[l], c.n_jacobi, P->ea[l],
                                        P->eb[l], l == 0 ? psi : nullptr, &e);
     if (rc) return rc;
+  }
+  if (use_cnn) {
+    Timed t(P, CTF_T_CNN);
+    CTF_HIP(cnn_apply_correction<double>(psi, P->cnn_out, P->cnn_scale, c.n, P->dims[0].nd, P->cnn_level,
+                                         P->stream));
   }
   // finest smoothing on the full equations
   double* cur = psi;
@@ -427,7 +474,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
 }
 
 // one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0)
-int inner_cycle32(ctf_problem* P, bool e_is_zero) {
+int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
   // inner residual r - A e (just r while e = 0)
@@ -442,6 +489,11 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero) {
     CTF_HIP(launch_restrict<float>(P->lf(l - 1), P->lf(l), l == 1 ? r0 : P->rho_f[l - 1], P->rho_f[l],
                                    P->stream));
   }
+  if (use_cnn) {
+    const int lc = P->cnn_level;
+    int rc = cnn_features_and_net<float>(P, P->lf(lc), lc == 0 ? r0 : P->rho_f[lc], true);
+    if (rc) return rc;
+  }
   const float* e = nullptr;
   for (int l = L - 1; l >= 0; --l) {
     const int xmode = (l == L - 1) ? 2 : 1;
@@ -452,6 +504,11 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero) {
                                       P->eb_f[l], (l == 0 && !e_is_zero) ? P->e_f : nullptr, &e,
                                       (l == 0 && e_is_zero) ? P->e_f : nullptr);
     if (rc) return rc;
+  }
+  if (use_cnn) {
+    Timed t(P, CTF_T_CNN);
+    CTF_HIP(cnn_apply_correction<float>(P->e_f, P->cnn_out, P->cnn_scale, c.n, P->dims[0].nd, P->cnn_level,
+                                        P->stream));
   }
   float* cur = P->e_f;
   float* other = P->e_tmp_f;
@@ -492,7 +549,7 @@ int outer_residual(ctf_problem* P, const double* psi, double* rel) {
 }
 
 // one refinement step after outer_residual: n_inner float32 cycles and the float64 update
-int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done) {
+int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_cnn = false) {
   const size_t n = P->dof(0);
   const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
   if (fas) {
@@ -505,7 +562,7 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done) {
   }
   int it = 0;
   for (; it < P->cfg.n_inner && it < max_inner; ++it) {
-    int rc = inner_cycle32(P, !fas && it == 0);
+    int rc = inner_cycle32(P, !fas && it == 0, use_cnn);
     if (rc) return rc;
   }
   if (it > 0) {
@@ -540,6 +597,8 @@ void ctf_default_config(ctf_config* c) {
   c->alpha_r = 3.0;
   c->eps_k = 1e-3;
   c->n_inner = 2;
+  c->cnn_level = -1;
+  c->cnn_max_growth = 1.0;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -637,6 +696,14 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
         return bail(fail(CTF_EHIP, "conversion failed"));
     if (launch_convert_d2f(P->sigma_s, P->sigma_s_f, nl * size_t(G) * G * nc0, s))
       return bail(fail(CTF_EHIP, "conversion failed"));
+  }
+  if (cfg->cnn_level >= 0) {
+    if (cfg->cnn_level >= P->L) return bail(fail(CTF_EINVAL, "cnn_level beyond the coarsest level"));
+    const int lc = cfg->cnn_level, nc = P->dims[lc].n;
+    P->cnn_level = lc;
+    if (cnn_static_features(P->sigt_d[lc], P->sigma_s, P->sigt_d[0], P->cnn_feat + size_t(nc) * nc,
+                            P->cnn_feat + 2 * size_t(nc) * nc, cfg->n, lc, P->dims[lc].h, s))
+      return bail(fail(CTF_EHIP, "learned-correction features failed"));
   }
   // ||b||_W with b = S / (4 pi): sum_n w_n = 4 pi, so ||b||^2 = h^2 sum S^2 / (4 pi)
   std::vector<double> src(G * nc0);
@@ -842,8 +909,10 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
   if (P->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !P->k_held)
     return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
   const auto t0 = std::chrono::steady_clock::now();
-  int cycles = 0, outer = 0, nhist = 0;
-  double rel = 0.0;
+  const size_t n = P->dof(0);
+  int cycles = 0, outer = 0, nhist = 0, applied = 0, rejected = 0;
+  double rel = 0.0, prev = 0.0;
+  bool last_used_cnn = false;
   int status = CTF_NOT_CONVERGED;
   for (;;) {
     int rc;
@@ -858,6 +927,15 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
         rel = nr / P->bnorm;
       }
     }
+    // plain multigrid is the fallback and the judge: a step with the learned correction that
+    // raised the residual (or made it non-finite) is undone and the correction switched off
+    if (last_used_cnn && (rc == CTF_ENONFINITE || (rc == CTF_OK && rel > P->cfg.cnn_max_growth * prev))) {
+      CTF_HIP(hipMemcpyAsync(psi, P->cnn_backup, n * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+      P->cnn_on = false;
+      rejected = 1;
+      last_used_cnn = false;
+      continue;
+    }
     if (rc) return rc;
     if (info && info->history && nhist < info->history_len) info->history[nhist] = rel;
     ++nhist;
@@ -866,17 +944,23 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
       break;
     }
     if (cycles >= max_cycles) break;
+    const bool use_cnn = P->cnn_on && P->cnn_ready;
+    if (use_cnn)
+      CTF_HIP(hipMemcpyAsync(P->cnn_backup, psi, n * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
     if (P->mixed()) {
       int done = 0;
-      rc = refine_rest(P, psi, max_cycles - cycles, &done);
+      rc = refine_rest(P, psi, max_cycles - cycles, &done, use_cnn);
       if (rc) return rc;
       cycles += done;
       ++outer;
     } else {
-      rc = cycle_rest64(P, psi);
+      rc = cycle_rest64(P, psi, use_cnn);
       if (rc) return rc;
       ++cycles;
     }
+    applied += use_cnn ? 1 : 0;
+    last_used_cnn = use_cnn;
+    prev = rel;
   }
   CTF_HIP(hipStreamSynchronize(P->stream));
   if (info) {
@@ -884,8 +968,84 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
     info->outer_steps = outer;
     info->rel_residual = rel;
     info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->cnn_applied = applied;
+    info->cnn_rejected = rejected;
   }
   return status;
+}
+
+int ctf_cnn_param_count(void) { return cnn_param_count(); }
+
+size_t ctf_cnn_workspace_bytes(int batch, int h, int w) {
+  if (batch < 1 || h < 1 || w < 1) return 0;
+  return cnn_workspace_bytes(batch, h, w);
+}
+
+int ctf_cnn_forward(const float* params, const float* in, float* out, int batch, int h, int w, int bf16,
+                    void* workspace, size_t ws_bytes, void* stream) {
+  if (!params || !in || !out || !workspace || batch < 1 || h < 1 || w < 1)
+    return fail(CTF_EINVAL, "bad argument");
+  if (ws_bytes < cnn_workspace_bytes(batch, h, w)) return fail(CTF_ENOMEM, "network workspace too small");
+  CTF_HIP(cnn_forward(params, in, out, batch, h, w, bf16, workspace, static_cast<hipStream_t>(stream)));
+  return CTF_OK;
+}
+
+int ctf_cnn_loss_grad(const float* params, const float* in, const float* target, int batch, int h, int w,
+                      int bf16, float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream) {
+  if (!params || !in || !target || !grad || !loss || !workspace || batch < 1 || h < 1 || w < 1)
+    return fail(CTF_EINVAL, "bad argument");
+  if (ws_bytes < cnn_workspace_bytes(batch, h, w)) return fail(CTF_ENOMEM, "network workspace too small");
+  CTF_HIP(cnn_loss_grad(params, in, target, batch, h, w, bf16, grad, loss, workspace,
+                        static_cast<hipStream_t>(stream)));
+  return CTF_OK;
+}
+
+int ctf_cnn_adam(float* params, float* m, float* v, const float* grad, int n, int step, float lr, void* stream) {
+  if (!params || !m || !v || !grad || n < 1 || step < 1) return fail(CTF_EINVAL, "bad argument");
+  CTF_HIP(cnn_adam(params, m, v, grad, n, step, lr, static_cast<hipStream_t>(stream)));
+  return CTF_OK;
+}
+
+int ctf_cnn_attach(ctf_problem* P, const float* params) {
+  if (!P || !params) return fail(CTF_EINVAL, "null argument");
+  if (P->cnn_level < 0) return fail(CTF_EINVAL, "problem created without cnn_level");
+  CTF_HIP(hipMemcpyAsync(P->cnn_params, params, size_t(cnn_param_count()) * sizeof(float),
+                         hipMemcpyDeviceToDevice, P->stream));
+  P->cnn_ready = true;
+  P->cnn_on = true;
+  return CTF_OK;
+}
+
+int ctf_cnn_enable(ctf_problem* P, int on) {
+  if (!P) return fail(CTF_EINVAL, "null argument");
+  if (on && !P->cnn_ready) return fail(CTF_EINVAL, "no network attached");
+  P->cnn_on = on != 0;
+  return CTF_OK;
+}
+
+int ctf_cnn_sample(ctf_problem* P, double* psi, const double* psi_star, float* features, float* target,
+                   double* scale) {
+  if (!P || !psi || !psi_star || !features || !target || !scale) return fail(CTF_EINVAL, "null argument");
+  if (P->cnn_level < 0) return fail(CTF_EINVAL, "problem created without cnn_level");
+  if (P->mixed()) return fail(CTF_EINVAL, "training samples come from float64 cycles");
+  int rc = emission64(P, psi, true);
+  if (rc) return rc;
+  rc = finest64(P, psi, P->rho[0], 0, 1.0);
+  if (rc) return rc;
+  rc = cycle_rest64(P, psi, false, true);
+  if (rc) return rc;
+  const int lc = P->cnn_level, nc = P->dims[lc].n;
+  CTF_HIP(hipMemcpyAsync(features, P->cnn_feat, 3 * size_t(nc) * nc * sizeof(float), hipMemcpyDeviceToDevice,
+                         P->stream));
+  // angle-integrated error after the cycle, averaged onto the correction grid
+  const size_t n = P->dof(0);
+  CTF_HIP(hipMemcpyAsync(P->psi_tmp, psi_star, n * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+  CTF_HIP(launch_axpy<double>(P->psi_tmp, psi, -1.0, n, P->stream));
+  CTF_HIP(launch_moments<double>(P->ld(0), P->psi_tmp, P->phi, 1, P->stream));
+  CTF_HIP(cnn_target(P->phi, target, P->cnn_scale, P->cfg.n, lc, P->stream));
+  CTF_HIP(hipMemcpyAsync(scale, P->cnn_scale, sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  CTF_HIP(hipStreamSynchronize(P->stream));
+  return CTF_OK;
 }
 
 int ctf_timing_enable(ctf_problem* P, int on, int capacity) {

@@ -153,4 +153,23 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s);
 // y(double) += u(float) - v(float)
 hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s);
 
+// ---- learned coarse-grid correction (cnn.hip) ---------------------------------------------------
+int cnn_param_count();
+size_t cnn_workspace_bytes(int B, int H, int W);
+hipError_t cnn_forward(const float* theta, const float* in, float* out, int B, int H, int W, int bf16,
+                       void* ws, hipStream_t s);
+hipError_t cnn_loss_grad(const float* theta, const float* in, const float* target, int B, int H, int W,
+                         int bf16, float* grad, double* loss, void* ws, hipStream_t s);
+hipError_t cnn_adam(float* theta, float* m, float* v, const float* g, int n, int step, float lr, hipStream_t s);
+// f0 = sum_n w_n rho_n on one level (group 0), normalised by its RMS (stored in scale[0])
+template <typename T>
+hipError_t cnn_scalar_residual(const LevelData<T>& L, const T* rho, float* f0, double* scale, hipStream_t s);
+// psi (finest, group 0) += scale * out(coarse cell) / (4 pi)
+template <typename T>
+hipError_t cnn_apply_correction(T* psi, const float* out, const double* scale, int n, int nd, int shift,
+                                hipStream_t s);
+hipError_t cnn_target(const double* phi_err, float* tgt, const double* scale, int n, int shift, hipStream_t s);
+hipError_t cnn_static_features(const double* st_c, const double* ss_f, const double* st_f, float* f1, float* f2,
+                               int n, int shift, double H, hipStream_t s);
+
 }  // namespace ctf

@@ -24,9 +24,11 @@ EXPORTED = [
     "ctf_level_sigma_t", "ctf_apply_operator", "ctf_moments", "ctf_freeze_k", "ctf_smooth",
     "ctf_restrict", "ctf_prolong", "ctf_mg_cycle", "ctf_solve", "ctf_norm", "ctf_last_error",
     "ctf_quadrature", "ctf_timing_enable", "ctf_timing_read", "ctf_moments_f32",
+    "ctf_cnn_param_count", "ctf_cnn_workspace_bytes", "ctf_cnn_forward", "ctf_cnn_loss_grad",
+    "ctf_cnn_adam", "ctf_cnn_attach", "ctf_cnn_enable", "ctf_cnn_sample",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
-                 "emission", "norm", "moments_mfma"]
+                 "emission", "norm", "moments_mfma", "cnn"]
 
 
 class Config(ctypes.Structure):
@@ -36,6 +38,7 @@ class Config(ctypes.Structure):
         ("bc", ctypes.c_int * 4), ("precision", ctypes.c_int), ("n_jacobi", ctypes.c_int),
         ("n_pg", ctypes.c_int), ("max_levels", ctypes.c_int), ("beta_pg", ctypes.c_double),
         ("alpha_r", ctypes.c_double), ("eps_k", ctypes.c_double), ("n_inner", ctypes.c_int),
+        ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double),
     ]
 
 
@@ -47,7 +50,8 @@ class LevelDesc(ctypes.Structure):
 class SolveInfo(ctypes.Structure):
     _fields_ = [("cycles", ctypes.c_int), ("outer_steps", ctypes.c_int),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int)]
+                ("history", ctypes.POINTER(ctypes.c_double)), ("history_len", ctypes.c_int),
+                ("cnn_applied", ctypes.c_int), ("cnn_rejected", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +84,14 @@ def load():
         "ctf_apply_operator": (I, [P, P, P, I]),
         "ctf_moments": (I, [P, P, P]),
         "ctf_moments_f32": (I, [P, P, P, I]),
+        "ctf_cnn_param_count": (I, []),
+        "ctf_cnn_workspace_bytes": (S, [I, I, I]),
+        "ctf_cnn_forward": (I, [P, P, P, I, I, I, I, P, S, P]),
+        "ctf_cnn_loss_grad": (I, [P, P, P, I, I, I, I, P, P, P, S, P]),
+        "ctf_cnn_adam": (I, [P, P, P, P, I, I, ctypes.c_float, P]),
+        "ctf_cnn_attach": (I, [P, P]),
+        "ctf_cnn_enable": (I, [P, I]),
+        "ctf_cnn_sample": (I, [P, P, P, P, P, ctypes.POINTER(D)]),
         "ctf_freeze_k": (I, [P, P, P, P]),
         "ctf_smooth": (I, [P, I, I, P, P, I]),
         "ctf_restrict": (I, [P, I, P, P]),
@@ -144,6 +156,44 @@ def quadrature(na):
     mu, nu, w = np.zeros(nd), np.zeros(nd), np.zeros(nd)
     _check(load().ctf_quadrature(na, mu.ctypes.data, nu.ctypes.data, w.ctypes.data))
     return mu, nu, w
+
+
+def cnn_param_count():
+    return load().ctf_cnn_param_count()
+
+
+class Cnn:
+    """Network kernels on caller-owned float32 device tensors (workspace sized per batch)."""
+
+    def __init__(self, batch, h, w, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        self.batch, self.h, self.w = batch, h, w
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        nb = self.lib.ctf_cnn_workspace_bytes(batch, h, w)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=device)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def _s(self):
+        return ctypes.c_void_p(self.stream.cuda_stream)
+
+    def forward(self, params, x, out, bf16=True):
+        b = x.shape[0]
+        _check(self.lib.ctf_cnn_forward(_ptr(params), _ptr(x), _ptr(out), b, self.h, self.w, int(bf16),
+                                        _ptr(self.ws), self.ws.numel(), self._s()))
+        return out
+
+    def loss_grad(self, params, x, target, grad, bf16=True):
+        b = x.shape[0]
+        _check(self.lib.ctf_cnn_loss_grad(_ptr(params), _ptr(x), _ptr(target), b, self.h, self.w, int(bf16),
+                                          _ptr(grad), _ptr(self.loss), _ptr(self.ws), self.ws.numel(),
+                                          self._s()))
+        return self.loss
+
+    def adam(self, params, m, v, grad, step, lr):
+        _check(self.lib.ctf_cnn_adam(_ptr(params), _ptr(m), _ptr(v), _ptr(grad), params.numel(), step,
+                                     ctypes.c_float(lr), self._s()))
 
 
 def _ptr(t):
@@ -259,7 +309,8 @@ class Problem:
         n = min(history_len, checks) if history_len else 0
         return {"converged": rc == CTF_OK, "cycles": info.cycles, "outer_steps": info.outer_steps,
                 "rel_residual": info.rel_residual, "seconds": info.seconds,
-                "history": hist[:n].copy() if history_len else None}
+                "history": hist[:n].copy() if history_len else None,
+                "cnn_applied": info.cnn_applied, "cnn_rejected": info.cnn_rejected}
 
     def timing_enable(self, on=True, capacity=4096):
         _check(self.lib.ctf_timing_enable(self.handle, int(on), capacity if on else 0))
@@ -273,6 +324,22 @@ class Problem:
                                             ctypes.byref(dr)))
             out[name] = (ms.value, n.value, dr.value)
         return out
+
+    # -- learned coarse-grid correction
+    def cnn_attach(self, params):
+        _check(self.lib.ctf_cnn_attach(self.handle, _ptr(params)))
+
+    def cnn_enable(self, on):
+        _check(self.lib.ctf_cnn_enable(self.handle, int(on)))
+
+    def cnn_grid(self):
+        return self.levels[self.cfg.cnn_level].n
+
+    def cnn_sample(self, psi, psi_star, features, target):
+        sc = ctypes.c_double(0.0)
+        _check(self.lib.ctf_cnn_sample(self.handle, _ptr(psi), _ptr(psi_star), _ptr(features), _ptr(target),
+                                       ctypes.byref(sc)))
+        return sc.value
 
     def norm(self, v):
         r = ctypes.c_double(0.0)

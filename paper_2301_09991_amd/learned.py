@@ -1,0 +1,99 @@
+"""Training driver of the learned coarse-grid correction (orchestration only: every sample, loss,
+gradient and Adam step is computed by the HIP library; PyTorch holds the device buffers).
+
+Samples come from the solver itself: for each seeded training problem the float64 cycle is run to
+a tight residual (psi*), then restarted from zero; at chosen cycles k the library records the
+network input of the cycle's starting residual and the angle-integrated error psi* - psi left
+after that plain cycle (both on the grid of the correction level, the error in units of the
+input's scale).  The network is trained on these pairs by mean-squared error with Adam.
+"""
+import numpy as np
+
+from . import ctf
+
+SAMPLE_CYCLES = (1, 2, 4, 8, 16, 32)
+
+
+def init_params(seed, device="cuda"):
+    """Seeded He-uniform weights (bound sqrt(6 / fan_in)), zero biases, flat float32 vector."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(seed))
+    chans = (3, 32, 32, 32, 1)
+    parts = []
+    for ci, co in zip(chans[:-1], chans[1:]):
+        bound = np.sqrt(6.0 / (ci * 9))
+        parts.append(rng.uniform(-bound, bound, size=co * ci * 9))
+        parts.append(np.zeros(co))
+    theta = np.concatenate(parts).astype(np.float32)
+    assert theta.size == ctf.cnn_param_count()
+    return torch.as_tensor(theta, device=device)
+
+
+def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=2, max_growth=1.0):
+    st, ss, src = inputs
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
+                             scatter_order=ss.shape[0] - 1, discretisation=disc,
+                             precision=precision, n_inner=n_inner, cnn_level=cnn_level,
+                             cnn_max_growth=max_growth)
+    return ctf.Problem(cfg, st, ss, src)
+
+
+def generate_samples(workloads, make_inputs, cnn_level=0, cycles=SAMPLE_CYCLES, star_rtol=1e-9,
+                     max_cycles=4000, disc=ctf.UPWIND):
+    """Features [S, 3, nc, nc] and targets [S, 1, nc, nc] (float32 device tensors)."""
+    import torch
+    feats, tgts = [], []
+    kmax = max(cycles)
+    for w in workloads:
+        prob = make_problem(w, make_inputs(w), cnn_level, disc=disc)
+        star = prob.zeros()
+        prob.solve(star, star_rtol, max_cycles)
+        nc = prob.cnn_grid()
+        psi = prob.zeros()
+        for k in range(1, kmax + 1):
+            if k in cycles:
+                f = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+                t = torch.empty((1, nc, nc), dtype=torch.float32, device="cuda")
+                prob.cnn_sample(psi, star, f, t)
+                feats.append(f)
+                tgts.append(t)
+            else:
+                prob.mg_cycle(psi)
+        del prob
+    return torch.stack(feats), torch.stack(tgts)
+
+
+def train(features, targets, epochs=60, batch=16, lr=1e-3, seed=0, bf16=True, log=None):
+    """Adam on the mean-squared error; returns (params, per-epoch mean training loss)."""
+    import torch
+    S, _, h, w = features.shape
+    net = ctf.Cnn(batch, h, w)
+    theta = init_params(seed)
+    m = torch.zeros_like(theta)
+    v = torch.zeros_like(theta)
+    grad = torch.zeros_like(theta)
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    history, step = [], 0
+    for ep in range(epochs):
+        perm = rng.permutation(S)
+        losses = []
+        for b0 in range(0, S - batch + 1, batch):
+            idx = torch.as_tensor(perm[b0:b0 + batch], device="cuda")
+            x = features.index_select(0, idx).contiguous()
+            t = targets.index_select(0, idx).contiguous()
+            loss = net.loss_grad(theta, x, t, grad, bf16=bf16)
+            step += 1
+            net.adam(theta, m, v, grad, step, lr)
+            losses.append(loss.item())
+        history.append(float(np.mean(losses)) if losses else float("nan"))
+        if log:
+            log(f"epoch {ep}: loss {history[-1]:.4e}")
+    return theta, history
+
+
+def evaluate_loss(theta, features, targets, bf16=True):
+    import torch
+    S, _, h, w = features.shape
+    net = ctf.Cnn(S, h, w)
+    grad = torch.zeros_like(theta)
+    return net.loss_grad(theta, features.contiguous(), targets.contiguous(), grad, bf16=bf16).item()

@@ -1,0 +1,138 @@
+"""The learned coarse-grid correction on the GPU: network kernels against the float64 oracle, the
+training driver, the solver's fallback, and what the trained network gains over plain multigrid.
+
+Tolerances: float32-activation mode 1e-4 relative (float32 sums of <= 288 products per layer);
+bf16 mode 5e-2 relative (every activation and weight rounded to 8 significant bits, four layers).
+"""
+import numpy as np
+import pytest
+
+from oracle import cnn as ocnn
+from workloads import Workload, make_inputs, random_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _lib():
+    from paper_2301_09991_amd import ctf, learned
+    return ctf, learned
+
+
+def _data(B=2, H=12, W=20, seed=5):
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(B, 3, H, W)).astype(np.float32)
+    t = rng.normal(size=(B, 1, H, W)).astype(np.float32)
+    theta = ocnn.init_params(seed).astype(np.float32)
+    theta[-1] = 0.05
+    return theta, x, t
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
+def test_forward_matches_oracle(bf16, tol):
+    import torch
+    ctf, _ = _lib()
+    theta, x, _ = _data()
+    net = ctf.Cnn(2, 12, 20)
+    out = torch.empty((2, 1, 12, 20), dtype=torch.float32, device="cuda")
+    net.forward(torch.as_tensor(theta, device="cuda"), torch.as_tensor(x, device="cuda"), out, bf16=bf16)
+    ref, _, _ = ocnn.forward(theta.astype(np.float64), x.astype(np.float64))
+    got = out.cpu().numpy()
+    assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
+def test_loss_and_gradient_match_oracle(bf16, tol):
+    import torch
+    ctf, _ = _lib()
+    theta, x, t = _data()
+    net = ctf.Cnn(2, 12, 20)
+    grad = torch.zeros(theta.size, dtype=torch.float32, device="cuda")
+    loss = net.loss_grad(torch.as_tensor(theta, device="cuda"), torch.as_tensor(x, device="cuda"),
+                         torch.as_tensor(t, device="cuda"), grad, bf16=bf16).item()
+    ref_loss, ref_g = ocnn.loss_and_grad(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    g = grad.cpu().numpy().astype(np.float64)
+    assert abs(loss - ref_loss) <= tol * ref_loss
+    assert np.linalg.norm(g - ref_g) <= tol * np.linalg.norm(ref_g)
+
+
+def test_adam_matches_oracle():
+    import torch
+    ctf, _ = _lib()
+    rng = np.random.default_rng(2)
+    n = ctf.cnn_param_count()
+    th = rng.normal(size=n).astype(np.float32)
+    m = rng.normal(size=n).astype(np.float32) * 0.1
+    v = rng.uniform(size=n).astype(np.float32) * 0.01
+    g = rng.normal(size=n).astype(np.float32)
+    tt, mm, vv = (torch.as_tensor(a.copy(), device="cuda") for a in (th, m, v))
+    net = ctf.Cnn(1, 4, 4)
+    net.adam(tt, mm, vv, torch.as_tensor(g, device="cuda"), 3, 1e-2)
+    rt, rm, rv = ocnn.adam_step(th.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                                g.astype(np.float64), 3, 1e-2)
+    assert np.allclose(tt.cpu().numpy(), rt, rtol=1e-5, atol=1e-6)
+    assert np.allclose(mm.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
+    assert np.allclose(vv.cpu().numpy(), rv, rtol=1e-5, atol=1e-9)
+
+
+def _wl(N, L, seed, na=2):
+    # scattering-dominated (c in [0.8, 0.99]) unit source in the central quarter, 4x4-cell patches
+    return Workload(f"learn_{seed}", N, L, 2, na, 1, max(1, N // 8), "iso", "box_quarter_phys",
+                    (0.8, 0.99), seed)
+
+
+@pytest.fixture(scope="module")
+def trained():
+    """60 seeded 32 x 32 problems (h = 0.25, c in [0.8, 0.99]), samples at cycles 1..32, Adam."""
+    _, learned = _lib()
+    train_w = [_wl(32, 8.0, 4000 + k) for k in range(60)]
+    F, T = learned.generate_samples(train_w, make_inputs, cnn_level=0)
+    theta, hist = learned.train(F, T, epochs=150, batch=16, lr=2e-3, seed=0)
+    return theta, hist, F, T
+
+
+def test_training_reduces_the_loss(trained):
+    theta, hist, F, T = trained
+    zero_loss = float((T ** 2).mean().item())
+    assert hist[-1] < 0.05 * zero_loss
+    assert hist[-1] < 0.2 * hist[0]
+
+
+@pytest.mark.parametrize("N,level", [(64, 1), (128, 2)])
+def test_trained_network_reduces_cycles(trained, N, level):
+    """Same cell size at the correction level as in training (H = 0.25); to 1e-6 with the learned
+    correction and its fallback, against plain multigrid on the same problem."""
+    theta = trained[0]
+    _, learned = _lib()
+    w = _wl(N, 8.0, 4900)
+    inp = make_inputs(w)
+    res = {}
+    for use in (False, True):
+        prob = learned.make_problem(w, inp, level)
+        if use:
+            prob.cnn_attach(theta)
+        psi = prob.zeros()
+        res[use] = (prob.solve(psi, 1e-6, 3000), psi)
+    plain, learned_ = res[False][0], res[True][0]
+    assert plain["converged"] and learned_["converged"]
+    assert learned_["cnn_applied"] >= 1
+    assert learned_["cycles"] < plain["cycles"], (learned_["cycles"], plain["cycles"])
+    # both reach the same discrete solution
+    a, b = res[True][1].cpu().numpy(), res[False][1].cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-5 * np.abs(b).max()
+
+
+def test_bad_network_falls_back_to_plain_multigrid():
+    import torch
+    _, learned = _lib()
+    w = _wl(32, 8.0, 4901)
+    inp = make_inputs(w)
+    prob = learned.make_problem(w, inp, 0)
+    bad = torch.as_tensor(random_field((19681,), seed=9, lo=-50.0, hi=50.0).astype(np.float32), device="cuda")
+    prob.cnn_attach(bad)
+    psi = prob.zeros()
+    info = prob.solve(psi, 1e-8, 3000)
+    assert info["converged"] and info["cnn_rejected"] == 1
+    ref = learned.make_problem(w, inp, 0)
+    psi_ref = ref.zeros()
+    ref.solve(psi_ref, 1e-8, 3000)
+    assert np.abs(psi.cpu().numpy() - psi_ref.cpu().numpy()).max() <= 1e-6 * psi_ref.abs().max().item()
