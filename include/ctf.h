@@ -76,6 +76,7 @@ typedef struct ctf_config {
   int cnn_level;       /* level of the learned coarse-grid correction, -1 = none (one group only) */
   double cnn_max_growth; /* the correction is switched off once a cycle applying it multiplies the
                             residual by more than this (default 1: it must not grow) */
+  int cnn_max_uses;      /* steps of a solve that may apply the correction (default 2) */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;
@@ -202,11 +203,13 @@ int ctf_norm(ctf_problem* prob, const double* v, double* out);
  * padding) maps three fields on the grid of level cnn_level -- the angle-integrated restricted
  * residual sum_n w_n rho_n divided by its RMS s, H sigma_t, and the mean scattering ratio -- to the
  * angle-integrated error left by a plain sawtooth cycle, in units of s.  In a cycle with the
- * correction, psi (or the float32 correction) gains s * net / (4 pi) in every ordinate, copied to
- * the fine cells, after the finest correction sweeps and before the finest smoothing.  In
+ * correction, psi (or the float32 correction) gains s * net / (4 pi) in every ordinate,
+ * interpolated bilinearly from the cell centres of that level to the finest cell centres, after the
+ * finest correction sweeps and before the finest smoothing.  In
  * ctf_solve plain multigrid stays the judge: a step with the correction that multiplies the
  * residual by more than cnn_max_growth (or makes it non-finite) is undone and the correction is
- * switched off for the rest of the solve.
+ * switched off for the rest of the solve; at most cnn_max_uses steps apply it (in a float32
+ * refinement step, only its first cycle).
  * Parameters: float32 device vector of ctf_cnn_param_count() values, W1 b1 W2 b2 W3 b3 W4 b4 with
  * W[c_out][c_in][ky][kx].  Activations: float32 [batch][channel][y][x]. */
 int ctf_cnn_param_count(void);

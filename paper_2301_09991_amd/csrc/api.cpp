@@ -562,7 +562,8 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   }
   int it = 0;
   for (; it < P->cfg.n_inner && it < max_inner; ++it) {
-    int rc = inner_cycle32(P, !fas && it == 0, use_cnn);
+    // the learned correction acts in the first float32 cycle of a refinement step only
+    int rc = inner_cycle32(P, !fas && it == 0, use_cnn && it == 0);
     if (rc) return rc;
   }
   if (it > 0) {
@@ -599,6 +600,7 @@ void ctf_default_config(ctf_config* c) {
   c->n_inner = 2;
   c->cnn_level = -1;
   c->cnn_max_growth = 1.0;
+  c->cnn_max_uses = 2;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -944,7 +946,7 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
       break;
     }
     if (cycles >= max_cycles) break;
-    const bool use_cnn = P->cnn_on && P->cnn_ready;
+    const bool use_cnn = P->cnn_on && P->cnn_ready && applied < P->cfg.cnn_max_uses;
     if (use_cnn)
       CTF_HIP(hipMemcpyAsync(P->cnn_backup, psi, n * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
     if (P->mixed()) {

@@ -384,7 +384,8 @@ __global__ __launch_bounds__(1024) void k_normalise(float* __restrict__ f0, int 
   if (threadIdx.x == 0) scale[0] = sc;
 }
 
-// psi[n][j][i] += scale * out[j >> shift][i >> shift] / (4 pi) for every ordinate
+// psi[n][j][i] += scale * out~(j, i) / (4 pi) for every ordinate, out~ the bilinear interpolation
+// of the coarse cell-centred field at the fine cell centre (constant beyond the outer centres)
 template <typename T>
 __global__ __launch_bounds__(kB) void k_apply_correction(T* __restrict__ psi, const float* __restrict__ out,
                                                          const double* __restrict__ scale, int n, int nd,
@@ -393,7 +394,15 @@ __global__ __launch_bounds__(kB) void k_apply_correction(T* __restrict__ psi, co
   const int c = blockIdx.x * kB + threadIdx.x;
   if (c >= ncell) return;
   const int j = c / n, i = c - j * n, nc = n >> shift;
-  const T add = T(scale[0] * double(out[(j >> shift) * nc + (i >> shift)]) * 0.07957747154594767);
+  const double inv = 1.0 / double(1 << shift);
+  const double ty = (j + 0.5) * inv - 0.5, tx = (i + 0.5) * inv - 0.5;
+  const int J0 = int(floor(ty)), I0 = int(floor(tx));
+  const double wy = ty - J0, wx = tx - I0;
+  const int ja = min(max(J0, 0), nc - 1), jb = min(max(J0 + 1, 0), nc - 1);
+  const int ia = min(max(I0, 0), nc - 1), ib = min(max(I0 + 1, 0), nc - 1);
+  const double v = (1 - wy) * ((1 - wx) * out[ja * nc + ia] + wx * out[ja * nc + ib]) +
+                   wy * ((1 - wx) * out[jb * nc + ia] + wx * out[jb * nc + ib]);
+  const T add = T(scale[0] * v * 0.07957747154594767);
   for (int d = 0; d < nd; ++d) psi[size_t(d) * ncell + c] += add;
 }
 

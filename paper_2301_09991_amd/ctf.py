@@ -38,7 +38,7 @@ class Config(ctypes.Structure):
         ("bc", ctypes.c_int * 4), ("precision", ctypes.c_int), ("n_jacobi", ctypes.c_int),
         ("n_pg", ctypes.c_int), ("max_levels", ctypes.c_int), ("beta_pg", ctypes.c_double),
         ("alpha_r", ctypes.c_double), ("eps_k", ctypes.c_double), ("n_inner", ctypes.c_int),
-        ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double),
+        ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double), ("cnn_max_uses", ctypes.c_int),
     ]
 
 

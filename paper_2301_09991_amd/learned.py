@@ -29,23 +29,28 @@ def init_params(seed, device="cuda"):
     return torch.as_tensor(theta, device=device)
 
 
-def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=2, max_growth=1.0):
+def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=2, max_growth=1.0,
+                 max_uses=2):
     st, ss, src = inputs
     cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
                              scatter_order=ss.shape[0] - 1, discretisation=disc,
                              precision=precision, n_inner=n_inner, cnn_level=cnn_level,
-                             cnn_max_growth=max_growth)
+                             cnn_max_growth=max_growth, cnn_max_uses=max_uses)
     return ctf.Problem(cfg, st, ss, src)
 
 
 def generate_samples(workloads, make_inputs, cnn_level=0, cycles=SAMPLE_CYCLES, star_rtol=1e-9,
                      max_cycles=4000, disc=ctf.UPWIND):
-    """Features [S, 3, nc, nc] and targets [S, 1, nc, nc] (float32 device tensors)."""
+    """Features [S, 3, nc, nc] and targets [S, 1, nc, nc] (float32 device tensors).
+
+    workloads: a list of workloads sampled at ``cnn_level``, or of (workload, level) pairs; all
+    must give the same correction grid nc = N / 2^level."""
     import torch
     feats, tgts = [], []
     kmax = max(cycles)
-    for w in workloads:
-        prob = make_problem(w, make_inputs(w), cnn_level, disc=disc)
+    for item in workloads:
+        w, lvl = item if isinstance(item, tuple) else (item, cnn_level)
+        prob = make_problem(w, make_inputs(w), lvl, disc=disc)
         star = prob.zeros()
         prob.solve(star, star_rtol, max_cycles)
         nc = prob.cnn_grid()

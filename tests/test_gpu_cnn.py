@@ -69,9 +69,10 @@ def test_adam_matches_oracle():
     net.adam(tt, mm, vv, torch.as_tensor(g, device="cuda"), 3, 1e-2)
     rt, rm, rv = ocnn.adam_step(th.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
                                 g.astype(np.float64), 3, 1e-2)
-    assert np.allclose(tt.cpu().numpy(), rt, rtol=1e-5, atol=1e-6)
-    assert np.allclose(mm.cpu().numpy(), rm, rtol=1e-5, atol=1e-7)
-    assert np.allclose(vv.cpu().numpy(), rv, rtol=1e-5, atol=1e-9)
+    # float32 arithmetic: 1 - beta2 is 1e-3 to 1.3e-5 relative in float32, so allow 5e-5
+    assert np.allclose(tt.cpu().numpy(), rt, rtol=5e-5, atol=1e-6)
+    assert np.allclose(mm.cpu().numpy(), rm, rtol=5e-5, atol=1e-7)
+    assert np.allclose(vv.cpu().numpy(), rv, rtol=5e-5, atol=1e-9)
 
 
 def _wl(N, L, seed, na=2):
