@@ -194,6 +194,32 @@ int ctf_mg_cycle(ctf_problem* prob, double* psi, double* rel_res);
  * Returns CTF_OK, CTF_NOT_CONVERGED, or an error (CTF_ENONFINITE on a NaN/Inf residual). */
 int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_solve_info* info);
 
+/* Solve nprob independent problems together (synchronous).  A solver step of every problem is
+ * captured once into one HIP graph (steps_per_graph steps per problem; problems spread over up to 8
+ * parallel branches); the graph is replayed until every problem has converged or max_steps steps
+ * were launched.  Convergence is decided on the device: each problem holds a flag that its step
+ * clears once ||rho||_W / ||b||_W <= rtol, after which all of that problem's kernels return at
+ * once, so converged problems drop out without host involvement; the host reads the flags only
+ * between replays.  psis[i] is problem i's angular flux (in place, warm start); infos (nprob
+ * entries, optional) receive per-problem cycles, outer steps, final residual and the call's wall
+ * time.  The problems must be distinct; their own streams must be idle.  Returns CTF_OK when all
+ * converged, CTF_NOT_CONVERGED otherwise. */
+int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, double rtol,
+                    int max_steps, int steps_per_graph, ctf_solve_info* infos);
+
+/* Launch shape of the finest-level kernels: rows per wavefront strip of the ConvFEM/PG kernels
+ * (8..512) and the block size of the upwind correction sweeps (multiple of 64, <= 1024). */
+int ctf_set_launch_shape(ctf_problem* prob, int strip_h, int corr_block);
+int ctf_get_launch_shape(const ctf_problem* prob, int* strip_h, int* corr_block);
+
+/* Autotuner: time the candidate launch shapes of the finest-level kernels on this problem's own
+ * buffers (strip heights 8..128 for ConvFEM/PG, sweep blocks 64..1024), keep the fastest, and
+ * record them in the JSON file cache_path under a key of (p, discretisation, precision, n, n_dir,
+ * groups).  A problem whose key is already cached takes the cached shape without timing unless
+ * force is set.  cache_path may be NULL (no file).  Synchronous; overwrites the problem's scratch
+ * buffers (not psi).  The chosen shape is returned through strip_h / corr_block (may be NULL). */
+int ctf_autotune(ctf_problem* prob, const char* cache_path, int force, int* strip_h, int* corr_block);
+
 /* ||v||_W of a finest-level array (synchronous). */
 int ctf_norm(ctf_problem* prob, const double* v, double* out);
 

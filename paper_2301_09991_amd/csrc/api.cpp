@@ -3,6 +3,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -125,6 +128,9 @@ struct ctf_problem {
   Stencils<float> st_f{};
   PGParams pp{};
   int bc_vac = 0;
+  int* active = nullptr;     // device flag read by every kernel (0: converged member of a batch)
+  int strip_h = 32;          // tuned launch shapes
+  int corr_block = 256;
   // learned coarse-grid correction
   int cnn_level = -1;
   bool cnn_on = false;
@@ -237,8 +243,10 @@ size_t layout(ctf_problem* P, char* base) {
     P->cnn_backup = c.take<double>(P->dof(0));
   }
   P->npartial = wnorm2_partials(P->dims[0]);
-  P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0])));
+  P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0], 8)));
   P->scal = c.take<double>(8);
+  P->active = c.take<int>(64);
+  for (int l = 0; l < P->L; ++l) P->dims[l].active = P->active;
   return c.off + 256;
 }
 
@@ -248,7 +256,7 @@ void init_dims(ctf_problem* P) {
   int n = c.n, na = c.na;
   double h = c.length / c.n;
   for (int l = 0; l < P->L; ++l) {
-    P->dims[l] = LevelDims{n, 8 * na * na, na, c.ngroups, h};
+    P->dims[l] = LevelDims{n, 8 * na * na, na, c.ngroups, h, nullptr};
     n /= 2;
     na = na > 1 ? na / 2 : 1;
     h *= 2.0;
@@ -317,13 +325,15 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   o.mode = mode;
   o.sign = sign;
   o.partial = (mode == 0 && want_norm) ? P->partial : nullptr;
+  o.strip_h = P->strip_h;
   {
     Timed t(P, CTF_T_PG64);
     CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, o, P->stream));
   }
   if (o.partial) {
     Timed t(P, CTF_T_NORM);
-    CTF_HIP(launch_sum_partials(P->partial, int(pg_partials(P->dims[0])), P->scal, P->stream));
+    CTF_HIP(launch_sum_partials(P->partial, int(pg_partials(P->dims[0], P->strip_h)), P->scal, P->stream,
+                                P->active));
   }
   return CTF_OK;
 }
@@ -361,7 +371,7 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
     T* dst = (last && final) ? final : ((s % 2 == 0) ? bufa : bufb);
     Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
     CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, nac, rhs, dst,
-                                        (last && acc) ? acc : nullptr, P->stream));
+                                        (last && acc) ? acc : nullptr, P->stream, P->corr_block));
     cur = dst;
     mode = 0;
   }
@@ -417,8 +427,7 @@ int cycle_rest64(ctf_problem* P, double* psi, bool use_cnn = false, bool feature
     if (rc) return rc;
     std::swap(cur, other);
   }
-  if (cur != psi)
-    CTF_HIP(hipMemcpyAsync(psi, cur, P->dof(0) * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+  if (cur != psi) CTF_HIP(launch_copy<double>(psi, cur, P->dof(0), P->stream, P->active));
   return CTF_OK;
 }
 
@@ -468,6 +477,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   o.rhs = P->r_f;
   o.mode = mode;
   o.sign = sign;
+  o.strip_h = P->strip_h;
   Timed t(P, CTF_T_PG32);
   CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, o, P->stream));
   return CTF_OK;
@@ -517,32 +527,34 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false) {
     if (rc) return rc;
     std::swap(cur, other);
   }
-  if (cur != P->e_f) std::swap(P->e_f, P->e_tmp_f);  // the result buffer becomes e_f
+  if (cur != P->e_f) CTF_HIP(launch_copy<float>(P->e_f, cur, P->dof(0), P->stream, P->active));
   return CTF_OK;
 }
 
 // Float64 residual of psi and its norm.  r_f receives rho64 rounded to float32 (linear forms) or
 // -rho64 (full-approximation form, see refine_rest).  Returns ||rho||_W / ||b||_W through rel.
-int outer_residual(ctf_problem* P, const double* psi, double* rel) {
+// the float64 residual and its squared norm (in P->scal[0]) without synchronising
+int outer_residual_async(ctf_problem* P, const double* psi) {
   int rc = emission64(P, psi, true);
   if (rc) return rc;
   const int disc = P->cfg.discretisation;
   const size_t n = P->dof(0);
-  double nr = 0.0;
-  if (disc == CTF_CONVFEM_PG) {
-    rc = finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, true);
-    if (rc) return rc;
-    rc = read_norm(P, &nr);
-  } else {
-    rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true, false);
-    if (rc) return rc;
-    CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream));
-    if (disc == CTF_CONVFEM_PG_FROZEN_K) {
-      CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream));
-      CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream));
-    }
-    if (!rc) rc = read_norm(P, &nr);
+  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, true);
+  rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true, false);
+  if (rc) return rc;
+  CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream, P->active));
+  if (disc == CTF_CONVFEM_PG_FROZEN_K) {
+    CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream, P->active));
+    CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream, P->active));
   }
+  return CTF_OK;
+}
+
+int outer_residual(ctf_problem* P, const double* psi, double* rel) {
+  int rc = outer_residual_async(P, psi);
+  if (rc) return rc;
+  double nr = 0.0;
+  rc = read_norm(P, &nr);
   if (rc) return rc;
   *rel = nr / P->bnorm;
   return CTF_OK;
@@ -555,8 +567,8 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   if (fas) {
     // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64), with
     // the diffusivities of psi64 left in kx_f, ky_f by the float64 residual
-    CTF_HIP(launch_convert_d2f(psi, P->psi32_f, n, P->stream));
-    CTF_HIP(hipMemcpyAsync(P->e_f, P->psi32_f, n * sizeof(float), hipMemcpyDeviceToDevice, P->stream));
+    CTF_HIP(launch_convert_d2f(psi, P->psi32_f, n, P->stream, P->active));
+    CTF_HIP(launch_copy<float>(P->e_f, P->psi32_f, n, P->stream, P->active));
     int rc = inner_finest32(P, P->psi32_f, P->r_f, 0, -1.0f);
     if (rc) return rc;
   }
@@ -567,16 +579,88 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
     if (rc) return rc;
   }
   if (it > 0) {
-    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, P->psi32_f, n, P->stream));
-    else CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream));
+    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, P->psi32_f, n, P->stream, P->active));
+    else CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream, P->active));
   }
   if (done) *done = it;
   return CTF_OK;
 }
 
+// One solver step with no host synchronisation (graph-capturable): residual and its norm, the
+// activity flag (0 once rel <= rtol; every later kernel of this problem then returns at once),
+// then the rest of the cycle / refinement step.
+int step_async(ctf_problem* P, double* psi, double rtol) {
+  int rc;
+  if (P->mixed()) {
+    rc = outer_residual_async(P, psi);
+  } else {
+    rc = emission64(P, psi, true);
+    if (!rc) rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true);
+  }
+  if (rc) return rc;
+  CTF_HIP(launch_update_active(P->scal, P->bnorm, rtol, P->scal + 1, P->active, P->scal + 2, P->stream));
+  return P->mixed() ? refine_rest(P, psi, P->cfg.n_inner, nullptr) : cycle_rest64(P, psi);
+}
+
 }  // namespace
 
 // ================================================================================================
+namespace {
+
+// milliseconds per call of fn (events on the problem's stream; 1 warm-up, then reps calls)
+template <typename F>
+int time_ms(ctf_problem* P, F&& fn, int reps, double* ms) {
+  hipEvent_t a, b;
+  CTF_HIP(hipEventCreate(&a));
+  CTF_HIP(hipEventCreate(&b));
+  int rc = fn();
+  if (!rc) {
+    (void)hipEventRecord(a, P->stream);
+    for (int r = 0; r < reps && !rc; ++r) rc = fn();
+    (void)hipEventRecord(b, P->stream);
+    (void)hipEventSynchronize(b);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, a, b);
+    *ms = double(t) / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return rc;
+}
+
+std::string tune_key(const ctf_problem* P) {
+  std::ostringstream k;
+  k << "p" << P->cfg.p << "_disc" << P->cfg.discretisation << "_prec" << P->cfg.precision << "_n" << P->cfg.n
+    << "_nd" << P->dims[0].nd << "_g" << P->cfg.ngroups;
+  return k.str();
+}
+
+// cache file: one JSON object, one entry per line: "key": {"strip_h": a, "corr_block": b, ...}
+std::map<std::string, std::string> read_cache(const char* path) {
+  std::map<std::string, std::string> m;
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    const size_t q0 = line.find('"');
+    if (q0 == std::string::npos) continue;
+    const size_t q1 = line.find('"', q0 + 1);
+    const size_t b0 = line.find('{', q1);
+    const size_t b1 = line.rfind('}');
+    if (q1 == std::string::npos || b0 == std::string::npos || b1 == std::string::npos || b1 < b0) continue;
+    m[line.substr(q0 + 1, q1 - q0 - 1)] = line.substr(b0, b1 - b0 + 1);
+  }
+  return m;
+}
+
+int field(const std::string& obj, const char* name, double* v) {
+  const std::string k = std::string("\"") + name + "\":";
+  const size_t p = obj.find(k);
+  if (p == std::string::npos) return 0;
+  return std::sscanf(obj.c_str() + p + k.size(), "%lf", v) == 1;
+}
+
+}  // namespace
+
 extern "C" {
 
 void ctf_default_config(ctf_config* c) {
@@ -699,6 +783,7 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
     if (launch_convert_d2f(P->sigma_s, P->sigma_s_f, nl * size_t(G) * G * nc0, s))
       return bail(fail(CTF_EHIP, "conversion failed"));
   }
+  if (launch_set_int(P->active, 1, s)) return bail(fail(CTF_EHIP, "flag init failed"));
   if (cfg->cnn_level >= 0) {
     if (cfg->cnn_level >= P->L) return bail(fail(CTF_EINVAL, "cnn_level beyond the coarsest level"));
     const int lc = cfg->cnn_level, nc = P->dims[lc].n;
@@ -817,6 +902,7 @@ int ctf_freeze_k(ctf_problem* P, const double* psi, double* kx, double* ky) {
   o.kx_out = P->kx;
   o.ky_out = P->ky;
   o.out = P->psi_tmp;
+  o.strip_h = P->strip_h;
   {
     Timed t(P, CTF_T_PG64);
     CTF_HIP(launch_pg<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, o, P->stream));
@@ -912,6 +998,7 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
     return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
   const auto t0 = std::chrono::steady_clock::now();
   const size_t n = P->dof(0);
+  CTF_HIP(launch_set_int(P->active, 1, P->stream));
   int cycles = 0, outer = 0, nhist = 0, applied = 0, rejected = 0;
   double rel = 0.0, prev = 0.0;
   bool last_used_cnn = false;
@@ -974,6 +1061,255 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
     info->cnn_rejected = rejected;
   }
   return status;
+}
+
+int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, double rtol, int max_steps,
+                    int steps_per_graph, ctf_solve_info* infos) {
+  if (!probs || !psis || nprob < 1 || max_steps < 0 || steps_per_graph < 1)
+    return fail(CTF_EINVAL, "bad argument");
+  for (int i = 0; i < nprob; ++i) {
+    if (!probs[i] || !psis[i]) return fail(CTF_EINVAL, "null problem or psi");
+    if (probs[i]->cfg.discretisation == CTF_CONVFEM_PG_FROZEN_K && !probs[i]->k_held)
+      return fail(CTF_EINVAL, "frozen-k discretisation needs ctf_freeze_k first");
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i]) return fail(CTF_EINVAL, "a problem appears twice in the batch");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  hipStream_t s0 = probs[0]->stream;
+  const int ns = std::min(nprob, 8);
+  std::vector<hipStream_t> streams(ns, nullptr);
+  std::vector<hipEvent_t> joins(ns, nullptr);
+  hipEvent_t fork = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> saved(nprob);
+  std::vector<bool> timing(nprob);
+  int rc = CTF_OK;
+  auto cleanup = [&]() {
+    for (int i = 0; i < nprob; ++i) {
+      probs[i]->stream = saved[i] ? saved[i] : probs[i]->stream;
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto e : joins)
+      if (e) (void)hipEventDestroy(e);
+    for (auto st : streams)
+      if (st) (void)hipStreamDestroy(st);
+  };
+  // every problem restarts active, with its step counter at zero; all prior work finished
+  for (int i = 0; i < nprob; ++i) {
+    ctf_problem* P = probs[i];
+    saved[i] = P->stream;
+    if (launch_set_int(P->active, 1, P->stream) != hipSuccess ||
+        hipMemsetAsync(P->scal, 0, 8 * sizeof(double), P->stream) != hipSuccess ||
+        hipStreamSynchronize(P->stream) != hipSuccess) {
+      cleanup();
+      return fail(CTF_EHIP, "batch initialisation failed");
+    }
+    saved[i] = nullptr;
+  }
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+    cleanup();
+    return fail(CTF_EHIP, "event creation failed");
+  }
+  for (int k = 0; k < ns; ++k)
+    if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&joins[k], hipEventDisableTiming) != hipSuccess) {
+      cleanup();
+      return fail(CTF_EHIP, "stream creation failed");
+    }
+  // capture: steps_per_graph steps of every problem, problems spread over ns parallel branches
+  if (hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    cleanup();
+    return fail(CTF_EHIP, "stream capture failed to start");
+  }
+  bool cap_ok = hipEventRecord(fork, s0) == hipSuccess;
+  for (int k = 0; k < ns && cap_ok; ++k) cap_ok = hipStreamWaitEvent(streams[k], fork, 0) == hipSuccess;
+  for (int i = 0; i < nprob && cap_ok && rc == CTF_OK; ++i) {
+    ctf_problem* P = probs[i];
+    saved[i] = P->stream;
+    timing[i] = P->timing;
+    P->timing = false;
+    P->stream = streams[i % ns];
+    for (int r = 0; r < steps_per_graph && rc == CTF_OK; ++r) rc = step_async(P, psis[i], rtol);
+    P->stream = saved[i];
+    P->timing = timing[i];
+    saved[i] = nullptr;
+  }
+  for (int k = 0; k < ns && cap_ok; ++k)
+    cap_ok = hipEventRecord(joins[k], streams[k]) == hipSuccess &&
+             hipStreamWaitEvent(s0, joins[k], 0) == hipSuccess;
+  const hipError_t ec = hipStreamEndCapture(s0, &graph);
+  if (rc != CTF_OK || !cap_ok || ec != hipSuccess) {
+    cleanup();
+    return rc != CTF_OK ? rc : fail(CTF_EHIP, "stream capture of the batched step failed");
+  }
+  if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    cleanup();
+    return fail(CTF_EHIP, "graph instantiation failed");
+  }
+  // replay until every problem is inactive (converged) or the step budget is spent
+  std::vector<double> host(3 * size_t(nprob));
+  std::vector<int> act(nprob, 1);
+  int launched = 0;
+  int status = CTF_NOT_CONVERGED;
+  while (launched < max_steps) {
+    if (hipGraphLaunch(exec, s0) != hipSuccess) {
+      cleanup();
+      return fail(CTF_EHIP, "graph launch failed");
+    }
+    launched += steps_per_graph;
+    for (int i = 0; i < nprob; ++i)
+      if (hipMemcpyAsync(&host[3 * i], probs[i]->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, s0) != hipSuccess ||
+          hipMemcpyAsync(&act[i], probs[i]->active, sizeof(int), hipMemcpyDeviceToHost, s0) != hipSuccess) {
+        cleanup();
+        return fail(CTF_EHIP, "status copy failed");
+      }
+    if (hipStreamSynchronize(s0) != hipSuccess) {
+      cleanup();
+      return fail(CTF_EHIP, "synchronisation failed");
+    }
+    bool any = false, bad = false;
+    for (int i = 0; i < nprob; ++i) {
+      any = any || act[i];
+      bad = bad || !std::isfinite(host[3 * i + 1]);
+    }
+    if (bad) {
+      cleanup();
+      return fail(CTF_ENONFINITE, "non-finite residual norm in the batch");
+    }
+    if (!any) {
+      status = CTF_OK;
+      break;
+    }
+  }
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (infos) {
+    for (int i = 0; i < nprob; ++i) {
+      const int steps = int(host[3 * i + 2]);
+      const bool mixed = probs[i]->mixed();
+      infos[i].cycles = mixed ? steps * probs[i]->cfg.n_inner : steps;
+      infos[i].outer_steps = mixed ? steps : 0;
+      infos[i].rel_residual = host[3 * i + 1];
+      infos[i].seconds = secs;
+      infos[i].cnn_applied = 0;
+      infos[i].cnn_rejected = 0;
+    }
+  }
+  cleanup();
+  return status;
+}
+
+int ctf_set_launch_shape(ctf_problem* P, int strip_h, int corr_block) {
+  if (!P) return fail(CTF_EINVAL, "null problem");
+  if (strip_h < 8 || strip_h > 512 || corr_block < 64 || corr_block > 1024 || corr_block % 64)
+    return fail(CTF_EINVAL, "strip_h in [8, 512], corr_block a multiple of 64 in [64, 1024]");
+  P->strip_h = strip_h;
+  P->corr_block = corr_block;
+  return CTF_OK;
+}
+
+int ctf_get_launch_shape(const ctf_problem* P, int* strip_h, int* corr_block) {
+  if (!P) return fail(CTF_EINVAL, "null problem");
+  if (strip_h) *strip_h = P->strip_h;
+  if (corr_block) *corr_block = P->corr_block;
+  return CTF_OK;
+}
+
+int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h, int* corr_block) {
+  if (!P) return fail(CTF_EINVAL, "null problem");
+  const std::string key = tune_key(P);
+  std::map<std::string, std::string> cache;
+  if (cache_path) cache = read_cache(cache_path);
+  auto it = cache.find(key);
+  double a = 0, b = 0;
+  if (!force && it != cache.end() && field(it->second, "strip_h", &a) && field(it->second, "corr_block", &b)) {
+    int rc = ctf_set_launch_shape(P, int(a), int(b));
+    if (rc) return rc;
+  } else {
+    const ctf_config& c = P->cfg;
+    const size_t n = P->dof(0);
+    // scratch inputs: zero fields (the timing does not depend on the values)
+    CTF_HIP(hipMemsetAsync(P->ea[0], 0, n * sizeof(double), P->stream));
+    CTF_HIP(hipMemsetAsync(P->eb[0], 0, n * sizeof(double), P->stream));
+    if (P->mixed()) {
+      CTF_HIP(hipMemsetAsync(P->ea_f[0], 0, n * sizeof(float), P->stream));
+      CTF_HIP(hipMemsetAsync(P->r_f, 0, n * sizeof(float), P->stream));
+      if (P->kx_f) {
+        CTF_HIP(hipMemsetAsync(P->kx_f, 0, n * sizeof(float), P->stream));
+        CTF_HIP(hipMemsetAsync(P->ky_f, 0, n * sizeof(float), P->stream));
+      }
+      CTF_HIP(hipMemsetAsync(P->E_f, 0, 3 * size_t(c.ngroups) * c.n * c.n * sizeof(float), P->stream));
+    }
+    int rc = emission64(P, P->ea[0], true);
+    if (rc) return rc;
+    const bool saved_timing = P->timing;
+    P->timing = false;
+    double best_pg = 1e30, best_corr = 1e30;
+    int best_h = P->strip_h, best_b = P->corr_block;
+    if (c.discretisation != CTF_UPWIND) {
+      for (int h : {8, 16, 32, 64, 128}) {
+        P->strip_h = h;
+        double ms = 0.0;
+        if (P->mixed()) {
+          PGLaunch<float> o;
+          o.psi = P->ea_f[0];
+          o.E = P->E_f;
+          o.nmomE = P->nmom;
+          o.kx_in = P->kx_f ? P->kx_f : P->ea_f[0];
+          o.ky_in = P->ky_f ? P->ky_f : P->ea_f[0];
+          o.out = P->eb_f[0];
+          o.rhs = P->r_f;
+          o.mode = 1;
+          o.strip_h = h;
+          rc = time_ms(P, [&]() -> int { return launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, o, P->stream)
+                                                     ? CTF_EHIP : CTF_OK; }, 5, &ms);
+        } else {
+          rc = time_ms(P, [&]() { return finest64(P, P->ea[0], P->eb[0], 1, 1.0); }, 5, &ms);
+        }
+        if (rc) break;
+        if (ms < best_pg) {
+          best_pg = ms;
+          best_h = h;
+        }
+      }
+    }
+    for (int bsz : {64, 128, 256, 512, 1024}) {
+      if (rc) break;
+      P->corr_block = bsz;
+      double ms = 0.0;
+      if (P->mixed())
+        rc = time_ms(P, [&]() -> int { return launch_upwind_correction<float>(P->lf(0), P->bc_vac, P->ea_f[0], 0, 1,
+                                                  P->r_f, P->eb_f[0], nullptr, P->stream, bsz) ? CTF_EHIP : CTF_OK; }, 5, &ms);
+      else
+        rc = time_ms(P, [&]() -> int { return launch_upwind_correction<double>(P->ld(0), P->bc_vac, P->ea[0], 0, 1,
+                                                  P->rho[0], P->eb[0], nullptr, P->stream, bsz) ? CTF_EHIP : CTF_OK; }, 5, &ms);
+      if (!rc && ms < best_corr) {
+        best_corr = ms;
+        best_b = bsz;
+      }
+    }
+    P->timing = saved_timing;
+    P->strip_h = best_h;
+    P->corr_block = best_b;
+    if (rc) return rc;
+    if (cache_path) {
+      std::ostringstream e;
+      e << "{\"strip_h\": " << best_h << ", \"corr_block\": " << best_b << ", \"pg_ms\": "
+        << (best_pg < 1e30 ? best_pg : 0.0) << ", \"corr_ms\": " << best_corr << "}";
+      cache[key] = e.str();
+      std::ofstream outf(cache_path, std::ios::trunc);
+      if (!outf) return fail(CTF_EINVAL, std::string("cannot write autotune cache ") + cache_path);
+      outf << "{\n";
+      size_t i = 0;
+      for (const auto& kv : cache) outf << "  \"" << kv.first << "\": " << kv.second << (++i < cache.size() ? ",\n" : "\n");
+      outf << "}\n";
+    }
+  }
+  if (strip_h) *strip_h = P->strip_h;
+  if (corr_block) *corr_block = P->corr_block;
+  return CTF_OK;
 }
 
 int ctf_cnn_param_count(void) { return cnn_param_count(); }

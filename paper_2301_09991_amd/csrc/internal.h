@@ -51,6 +51,7 @@ struct LevelDims {
   int na;
   int G;
   double h;
+  const int* active;  // device flag: kernels of a converged problem return at once (may be null)
 };
 
 template <typename T>
@@ -106,12 +107,13 @@ struct PGLaunch {
   const T* rhs = nullptr;
   int mode = 0;
   T sign = T(1);
+  int strip_h = 32;   // rows per wavefront strip (tunable)
 };
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
                      const PGLaunch<T>& o, hipStream_t s);
-// number of per-block partial sums a mode-0 launch_pg writes
-size_t pg_partials(const LevelDims& d);
+// number of per-block partial sums a mode-0 launch_pg writes with this strip height
+size_t pg_partials(const LevelDims& d, int strip_h);
 
 // Finest upwind operator: mode 0 out = sign * rho, mode 1 out = psi + rho / d.
 template <typename T>
@@ -123,7 +125,8 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 //   2: e = 0.   psi_acc != null: psi_acc += e_new instead of writing x_out.
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
-                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s);
+                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
+                                    int block = 256);
 
 template <typename T>
 hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine,
@@ -138,20 +141,30 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
                          double* out, hipStream_t s);
 int wnorm2_partials(const LevelDims& d);
 // out[0] = sum of np partials in a fixed order
-hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s);
+hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s,
+                               const int* active = nullptr);
+// if *active: rel[0] = sqrt(norm2[0]) / bnorm, *active = (rel > rtol), and steps[0] += 1 while
+// still active (batched solves)
+hipError_t launch_update_active(const double* norm2, double bnorm, double rtol, double* rel, int* active,
+                                double* steps, hipStream_t s);
+hipError_t launch_set_int(int* p, int v, hipStream_t s);
+template <typename T>
+hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t s, const int* active = nullptr);
 
 template <typename T>
-hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s);
+hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s, const int* active = nullptr);
 
 hipError_t launch_harmonic_coarsen(const double* fine, double* coarse, int G, int nc, hipStream_t s);
 
 // precision conversions
-hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s);
+hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s,
+                              const int* active = nullptr);
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s);
 // y(double) += x(float)
-hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s);
+hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, const int* active = nullptr);
 // y(double) += u(float) - v(float)
-hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s);
+hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s,
+                               const int* active = nullptr);
 
 // ---- learned coarse-grid correction (cnn.hip) ---------------------------------------------------
 int cnn_param_count();

@@ -11,6 +11,8 @@ namespace {
 
 constexpr int kBlock = 256;
 
+__device__ __forceinline__ bool idle(const int* active) { return active && *active == 0; }
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
 template <typename T>
@@ -45,6 +47,7 @@ constexpr int kMomCells = 64;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __restrict__ psi,
                                                      T* __restrict__ phi, int nmom) {
+  if (idle(L.dims.active)) return;
   const int ncell = L.dims.n * L.dims.n;
   const int lane = threadIdx.x % kMomCells, q = threadIdx.x / kMomCells;
   const int cell = blockIdx.x * kMomCells + lane;
@@ -117,6 +120,7 @@ __device__ __forceinline__ float bf16_to_float(unsigned short b) {
 
 __global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, const float* __restrict__ psi,
                                                           float* __restrict__ phi, int nmom) {
+  if (idle(L.dims.active)) return;
   const int ncell = L.dims.n * L.dims.n;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
   const int c0 = blockIdx.x * 64;
@@ -176,6 +180,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __restrict__ phi,
                                                       const T* __restrict__ ss, int nl,
                                                       const T* __restrict__ src, T* __restrict__ E) {
+  if (idle(d.active)) return;
   const size_t ncell = size_t(d.n) * d.n;
   const size_t t = size_t(blockIdx.x) * kBlock + threadIdx.x;
   const int g = blockIdx.y, G = d.G;
@@ -220,6 +225,7 @@ struct PGArgs {
   int mode;
   T sign;
   int ntx;
+  int strip_h;
   float* out_f;       // optional float copy of the output (mode 0)
   double* partial;    // optional per-block sum of w_n h^2 out^2 (mode 0)
   float* kx_out_f;    // optional float copies of the computed diffusivities
@@ -232,7 +238,6 @@ struct PGArgs {
 // (row buffer in LDS) followed by a y-pass over a rolling window of x-pass results held in
 // registers, so every input value is read from HBM about once.
 constexpr int kStripW = 64;
-constexpr int kStripH = 32;
 
 template <typename T, int W>
 __device__ __forceinline__ void push(T (&w)[W], T v) {
@@ -254,6 +259,7 @@ __device__ __forceinline__ T ypass(const T (&w)[W], const T* c) {
 //   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
 template <int P, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
+  if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;
   __shared__ T s_psi[RW];
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   __shared__ T s_ky[RW];
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * kStripH;
+  const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
   const int dir = blockIdx.y, g = blockIdx.z;
   const size_t ncell = size_t(n) * n;
   const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
@@ -284,7 +290,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
   const bool zx0 = (c0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c0 >= n && (a.bc_vac & 2) && mu < T(0));
   const bool zx1 = (c1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c1 >= n && (a.bc_vac & 2) && mu < T(0));
-  const int yend = min(y0 + kStripH, n);
+  const int yend = min(y0 + a.strip_h, n);
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
   // row values are loaded one row ahead so that the loads overlap the filtering of a row
@@ -382,6 +388,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
 // The strip reads 64 + 4P columns, and writes k for its inner 64 - 2P columns.
 template <int P, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
+  if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
@@ -390,7 +397,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   __shared__ T s_gy[kStripW];
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * kStripH;
+  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
   const int x0 = xs - P;                 // column of lane 0 (Psi is formed for x0 .. x0 + 63)
   const int dir = blockIdx.y, g = blockIdx.z;
   const size_t ncell = size_t(n) * n;
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   const bool zx1 = (c1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c1 >= n && (a.bc_vac & 2) && mu < T(0));
   const int gi = x0 + lane;
   const bool writer = lane >= P && lane < kStripW - P && gi < n && gi < xs + OW;
-  const int yend = min(y0 + kStripH, n);
+  const int yend = min(y0 + a.strip_h, n);
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
   T p0, p1 = 0;
   auto load_row = [&](int r, T& vp0, T& vp1) {
@@ -487,6 +494,7 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
                                                          const T* __restrict__ E, int nmomE,
                                                          T* __restrict__ out, int mode, T sign,
                                                          const T* __restrict__ rhs) {
+  if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const size_t ncell = size_t(n) * n;
   const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
@@ -514,13 +522,14 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
 
 // correction sweep on one level: e_new = e + (rhs - A_up e - sigma_t e) / d
 template <typename T, int XMODE>
-__global__ __launch_bounds__(kBlock) void k_upwind_corr(LevelData<T> L, int bc_vac,
+__global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
                                                          const T* __restrict__ xin, int nac,
                                                          const T* __restrict__ rhs,
                                                          T* __restrict__ xout, T* __restrict__ acc) {
+  if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const size_t ncell = size_t(n) * n;
-  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  const int cell = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
   if (cell >= int(ncell)) return;
   const int dir = blockIdx.y, g = blockIdx.z;
   const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
@@ -557,6 +566,7 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<T> Lc,
                                                       const T* __restrict__ fine,
                                                       T* __restrict__ coarse) {
+  if (idle(Lf.dims.active)) return;
   const int nc = Lc.dims.n, ndc = Lc.dims.nd, nf = Lf.dims.n, naf = Lf.dims.na;
   const size_t nccell = size_t(nc) * nc, nfcell = size_t(nf) * nf;
   const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
@@ -604,6 +614,7 @@ constexpr int kNormBlocks = 1024;
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_wnorm2_partial(LevelData<T> L, const T* __restrict__ v,
                                                             double* __restrict__ partial) {
+  if (idle(L.dims.active)) return;
   const size_t ncell = size_t(L.dims.n) * L.dims.n;
   const size_t total = ncell * L.dims.nd * L.dims.G;
   double acc = 0.0;
@@ -624,7 +635,8 @@ __global__ __launch_bounds__(kBlock) void k_wnorm2_partial(LevelData<T> L, const
 }
 
 __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partial, int np,
-                                                          double* __restrict__ out) {
+                                                          double* __restrict__ out, const int* active) {
+  if (idle(active)) return;
   __shared__ double red[kBlock];
   double acc = 0.0;
   for (int i = threadIdx.x; i < np; i += kBlock) acc += partial[i];
@@ -639,7 +651,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy(T* __restrict__ y, const T* __restrict__ x, T a,
-                                                  size_t n) {
+                                                  size_t n, const int* active) {
+  if (idle(active)) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) y[i] += a * x[i];
 }
@@ -659,7 +672,8 @@ __global__ __launch_bounds__(kBlock) void k_harmonic(const double* __restrict__ 
 }
 
 __global__ __launch_bounds__(kBlock) void k_d2f(const double* __restrict__ in, float* __restrict__ out,
-                                                 size_t n) {
+                                                 size_t n, const int* active) {
+  if (idle(active)) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) out[i] = float(in[i]);
 }
@@ -669,15 +683,40 @@ __global__ __launch_bounds__(kBlock) void k_f2d(const float* __restrict__ in, do
   if (i < n) out[i] = double(in[i]);
 }
 __global__ __launch_bounds__(kBlock) void k_add_f2d(double* __restrict__ y, const float* __restrict__ x,
-                                                     size_t n) {
+                                                     size_t n, const int* active) {
+  if (idle(active)) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) y[i] += double(x[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_add_diff_f2d(double* __restrict__ y, const float* __restrict__ u,
-                                                          const float* __restrict__ v, size_t n) {
+                                                          const float* __restrict__ v, size_t n,
+                                                          const int* active) {
+  if (idle(active)) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) y[i] += double(u[i]) - double(v[i]);
+}
+
+__global__ void k_update_active(const double* __restrict__ norm2, double bnorm, double rtol,
+                                double* __restrict__ rel, int* __restrict__ active, double* __restrict__ steps) {
+  if (threadIdx.x != 0 || *active == 0) return;
+  const double r = sqrt(norm2[0]) / bnorm;
+  rel[0] = r;
+  const int on = (r > rtol || r != r) ? 1 : 0;
+  *active = on;
+  if (on && steps) steps[0] += 1.0;
+}
+
+__global__ void k_set_int(int* p, int v) {
+  if (threadIdx.x == 0) *p = v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n,
+                                                  const int* active) {
+  if (idle(active)) return;
+  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < n) dst[i] = src[i];
 }
 
 inline unsigned nblocks(size_t total) { return unsigned((total + kBlock - 1) / kBlock); }
@@ -728,6 +767,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.rhs = o.rhs;
   a.mode = o.mode;
   a.sign = o.sign;
+  a.strip_h = o.strip_h;
   const int n = L.dims.n;
   if (!o.kx_in) {
     // diffusivities of psi first (into kx_out / ky_out, and / or their float copies)
@@ -738,7 +778,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
     a.ky_out_f = o.ky_out_f;
     const int ow = kStripW - 2 * p;
     a.ntx = (n + ow - 1) / ow;
-    const dim3 grid(a.ntx * ((n + kStripH - 1) / kStripH), L.dims.nd, L.dims.G);
+    const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
     switch (p) {
       case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
@@ -757,7 +797,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.out_f = o.out_f;
   a.partial = o.partial;
   a.ntx = (n + kStripW - 1) / kStripW;
-  const dim3 grid(a.ntx * ((n + kStripH - 1) / kStripH), L.dims.nd, L.dims.G);
+  const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_pg_stream<1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_pg_stream<2, T>), grid, dim3(kStripW), 0, s, a); break;
@@ -767,8 +807,8 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   return hipGetLastError();
 }
 
-size_t pg_partials(const LevelDims& d) {
-  const size_t strips = size_t((d.n + kStripW - 1) / kStripW) * ((d.n + kStripH - 1) / kStripH);
+size_t pg_partials(const LevelDims& d, int strip_h) {
+  const size_t strips = size_t((d.n + kStripW - 1) / kStripW) * ((d.n + strip_h - 1) / strip_h);
   return strips * d.nd * d.G;
 }
 
@@ -783,8 +823,9 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
-                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s) {
-  const dim3 grid(nblocks(size_t(L.dims.n) * L.dims.n), L.dims.nd, L.dims.G), blk(kBlock);
+                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
+  const size_t nc = size_t(L.dims.n) * L.dims.n;
+  const dim3 grid(unsigned((nc + block - 1) / block), L.dims.nd, L.dims.G), blk(block);
   if (xmode == 0)
     hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
   else if (xmode == 1)
@@ -815,18 +856,37 @@ template <typename T>
 hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int npartial,
                          double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_wnorm2_partial<T>, dim3(npartial), dim3(kBlock), 0, s, L, v, partial);
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, npartial, out);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, npartial, out, L.dims.active);
   return hipGetLastError();
 }
 
-hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, np, out);
+hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s, const int* active) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, np, out, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_update_active(const double* norm2, double bnorm, double rtol, double* rel, int* active,
+                                double* steps, hipStream_t s) {
+  hipLaunchKernelGGL(k_update_active, dim3(1), dim3(64), 0, s, norm2, bnorm, rtol, rel, active, steps);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_axpy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, a, n);
+hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t s, const int* active) {
+  hipLaunchKernelGGL(k_copy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, dst, src, n, active);
+  return hipGetLastError();
+}
+template hipError_t launch_copy<double>(double*, const double*, size_t, hipStream_t, const int*);
+template hipError_t launch_copy<float>(float*, const float*, size_t, hipStream_t, const int*);
+
+template <typename T>
+hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s, const int* active) {
+  hipLaunchKernelGGL(k_axpy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, a, n, active);
   return hipGetLastError();
 }
 
@@ -836,20 +896,21 @@ hipError_t launch_harmonic_coarsen(const double* fine, double* coarse, int G, in
   return hipGetLastError();
 }
 
-hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_d2f, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n);
+hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s, const int* active) {
+  hipLaunchKernelGGL(k_d2f, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n, active);
   return hipGetLastError();
 }
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n);
   return hipGetLastError();
 }
-hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, v, n);
+hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s,
+                               const int* active) {
+  hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, v, n, active);
   return hipGetLastError();
 }
-hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s) {
-  hipLaunchKernelGGL(k_add_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, n);
+hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, const int* active) {
+  hipLaunchKernelGGL(k_add_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, n, active);
   return hipGetLastError();
 }
 
@@ -862,13 +923,13 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s) {
   template hipError_t launch_upwind_full<T>(const LevelData<T>&, int, const T*, const T*, int, T*,  \
                                             int, T, const T*, hipStream_t);                         \
   template hipError_t launch_upwind_correction<T>(const LevelData<T>&, int, const T*, int, int,     \
-                                                  const T*, T*, T*, hipStream_t);                   \
+                                                  const T*, T*, T*, hipStream_t, int);              \
   template hipError_t launch_restrict<T>(const LevelData<T>&, const LevelData<T>&, const T*, T*,    \
                                          hipStream_t);                                              \
   template hipError_t launch_prolong<T>(const LevelData<T>&, int, const T*, T*, hipStream_t);       \
   template hipError_t launch_wnorm2<T>(const LevelData<T>&, const T*, double*, int, double*,        \
                                        hipStream_t);                                                \
-  template hipError_t launch_axpy<T>(T*, const T*, T, size_t, hipStream_t);
+  template hipError_t launch_axpy<T>(T*, const T*, T, size_t, hipStream_t, const int*);
 
 CTF_INSTANTIATE(double)
 CTF_INSTANTIATE(float)

@@ -26,6 +26,7 @@ EXPORTED = [
     "ctf_quadrature", "ctf_timing_enable", "ctf_timing_read", "ctf_moments_f32",
     "ctf_cnn_param_count", "ctf_cnn_workspace_bytes", "ctf_cnn_forward", "ctf_cnn_loss_grad",
     "ctf_cnn_adam", "ctf_cnn_attach", "ctf_cnn_enable", "ctf_cnn_sample",
+    "ctf_solve_batch", "ctf_set_launch_shape", "ctf_get_launch_shape", "ctf_autotune",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
                  "emission", "norm", "moments_mfma", "cnn"]
@@ -92,6 +93,10 @@ def load():
         "ctf_cnn_attach": (I, [P, P]),
         "ctf_cnn_enable": (I, [P, I]),
         "ctf_cnn_sample": (I, [P, P, P, P, P, ctypes.POINTER(D)]),
+        "ctf_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), D, I, I, ctypes.POINTER(SolveInfo)]),
+        "ctf_set_launch_shape": (I, [P, I, I]),
+        "ctf_get_launch_shape": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ctf_autotune": (I, [P, ctypes.c_char_p, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
         "ctf_freeze_k": (I, [P, P, P, P]),
         "ctf_smooth": (I, [P, I, I, P, P, I]),
         "ctf_restrict": (I, [P, I, P, P]),
@@ -156,6 +161,19 @@ def quadrature(na):
     mu, nu, w = np.zeros(nd), np.zeros(nd), np.zeros(nd)
     _check(load().ctf_quadrature(na, mu.ctypes.data, nu.ctypes.data, w.ctypes.data))
     return mu, nu, w
+
+
+def solve_batch(problems, psis, rtol, max_steps, steps_per_graph=1):
+    """Solve several problems with one captured HIP graph (ctf_solve_batch)."""
+    n = len(problems)
+    lib = load()
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    ps = (ctypes.c_void_p * n)(*[t.data_ptr() for t in psis])
+    infos = (SolveInfo * n)()
+    rc = _check(lib.ctf_solve_batch(hs, n, ps, rtol, max_steps, steps_per_graph, infos),
+                allow_not_converged=True)
+    return rc == CTF_OK, [{"cycles": i.cycles, "outer_steps": i.outer_steps, "rel_residual": i.rel_residual,
+                           "seconds": i.seconds} for i in infos]
 
 
 def cnn_param_count():
@@ -324,6 +342,21 @@ class Problem:
                                             ctypes.byref(dr)))
             out[name] = (ms.value, n.value, dr.value)
         return out
+
+    # -- launch shapes
+    def set_launch_shape(self, strip_h, corr_block):
+        _check(self.lib.ctf_set_launch_shape(self.handle, strip_h, corr_block))
+
+    def launch_shape(self):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.ctf_get_launch_shape(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def autotune(self, cache_path=None, force=False):
+        a, b = ctypes.c_int(), ctypes.c_int()
+        path = cache_path.encode() if cache_path else None
+        _check(self.lib.ctf_autotune(self.handle, path, int(force), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
 
     # -- learned coarse-grid correction
     def cnn_attach(self, params):

@@ -1,0 +1,94 @@
+"""Batched solves in one captured HIP graph, launch-shape independence, and the autotuner."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from pairs import make_pair, workload
+from workloads import Workload, batch_workloads, make_inputs, random_field
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctf():
+    from paper_2301_09991_amd import ctf
+    return ctf
+
+
+def _problem(w, precision, disc=0):
+    ctf = _ctf()
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G, scatter_order=0,
+                             discretisation=disc, precision=precision)
+    return ctf.Problem(cfg, st, ss, src)
+
+
+@pytest.mark.parametrize("precision,steps_per_graph", [(0, 1), (1, 3)])
+def test_batch_equals_individual_solves(precision, steps_per_graph):
+    """Uneven problems (batched recipe: p = 2, 4x4-cell patches, central source) solved together
+    by graph replays give exactly the iterates of their individual solves, every problem stopping
+    at its own convergence step."""
+    ctf = _ctf()
+    sizes = [16, 24, 32, 48, 40, 20]
+    ws = [Workload(f"b{k}", N, 1.0, 2, 2, 1, 4, "iso", "box_quarter", seed=3000 + k) for k, N in enumerate(sizes)]
+    probs = [_problem(w, precision) for w in ws]
+    psis = [p.zeros() for p in probs]
+    ok, infos = ctf.solve_batch(probs, psis, 1e-6, 400, steps_per_graph)
+    assert ok
+    for w, psi, info in zip(ws, psis, infos):
+        ref = _problem(w, precision)
+        x = ref.zeros()
+        r = ref.solve(x, 1e-6, 400)
+        assert r["converged"] and info["rel_residual"] <= 1e-6
+        assert info["cycles"] == r["cycles"]
+        assert abs(info["rel_residual"] - r["rel_residual"]) <= 1e-12 * r["rel_residual"]
+        assert np.array_equal(psi.cpu().numpy(), x.cpu().numpy())
+
+
+def test_batch_workload_sizes():
+    ws = batch_workloads()
+    assert len(ws) == 64
+    assert set(w.N for w in ws) <= {64, 96, 128, 192, 256, 384}
+    assert len(set(w.seed for w in ws)) == 64
+
+
+@pytest.mark.parametrize("disc,precision", [(1, 0), (1, 1), (2, 0)])
+def test_results_do_not_depend_on_launch_shape(disc, precision):
+    """The strip height and the sweep block size change only the launch decomposition: operator,
+    sweeps and cycles agree bit for bit."""
+    ctf = _ctf()
+    names = {0: "upwind", 1: "pg", 2: "pg_frozen"}
+    op, gp = make_pair(workload(N=72, na=2, G=2, scatter="downscatter"), names[disc], "vac",
+                       precision=precision)
+    psi = gp.empty()
+    psi.copy_(__import__("torch").as_tensor(random_field(op.shape(), seed=4, lo=0.0, hi=1.0)))
+    if disc == 2:
+        gp.freeze_k(psi)
+    outs = []
+    for strip_h, block in ((32, 256), (8, 64), (128, 1024)):
+        gp.set_launch_shape(strip_h, block)
+        out = gp.empty()
+        gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+        x = psi.clone()
+        for _ in range(2):
+            gp.mg_cycle(x)
+        outs.append((out.cpu().numpy(), x.cpu().numpy()))
+    for o, x in outs[1:]:
+        assert np.array_equal(o, outs[0][0]) and np.array_equal(x, outs[0][1])
+
+
+def test_autotune_picks_and_caches_a_shape():
+    ctf = _ctf()
+    w = Workload("tune", 96, 1.0, 2, 4, 1, 8, "iso", "box_quarter", seed=3)
+    prob = _problem(w, ctf.FP32_IR, disc=ctf.CONVFEM_PG)
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.json")
+        h, b = prob.autotune(path)
+        assert h in (8, 16, 32, 64, 128) and b in (64, 128, 256, 512, 1024)
+        assert os.path.exists(path)
+        text = open(path).read()
+        assert '"strip_h": %d' % h in text
+        other = _problem(w, ctf.FP32_IR, disc=ctf.CONVFEM_PG)
+        assert other.autotune(path) == (h, b)
+        assert other.launch_shape() == (h, b)
