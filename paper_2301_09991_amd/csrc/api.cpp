@@ -1075,7 +1075,7 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
       if (probs[j] == probs[i]) return fail(CTF_EINVAL, "a problem appears twice in the batch");
   }
   const auto t0 = std::chrono::steady_clock::now();
-  hipStream_t s0 = probs[0]->stream;
+  hipStream_t s0 = nullptr;  // the capture origin: a stream of our own (the default stream cannot be captured)
   const int ns = std::min(nprob, 8);
   std::vector<hipStream_t> streams(ns, nullptr);
   std::vector<hipEvent_t> joins(ns, nullptr);
@@ -1096,6 +1096,7 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
       if (e) (void)hipEventDestroy(e);
     for (auto st : streams)
       if (st) (void)hipStreamDestroy(st);
+    if (s0) (void)hipStreamDestroy(s0);
   };
   // every problem restarts active, with its step counter at zero; all prior work finished
   for (int i = 0; i < nprob; ++i) {
@@ -1109,9 +1110,10 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
     }
     saved[i] = nullptr;
   }
-  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) {
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess ||
+      hipStreamCreateWithFlags(&s0, hipStreamNonBlocking) != hipSuccess) {
     cleanup();
-    return fail(CTF_EHIP, "event creation failed");
+    return fail(CTF_EHIP, "event / stream creation failed");
   }
   for (int k = 0; k < ns; ++k)
     if (hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking) != hipSuccess ||
