@@ -84,6 +84,86 @@ print(json.dumps({"dof": w.dof, "cycles": cycles, "seconds": dt}))
                       f"{r['seconds']:.1f} s"}
 
 
+def time_to_tolerance(log):
+    """Learned-correction workload (1024 x 1024 nodes, L = 32, p = 2, 512 ordinates, one group,
+    c in [0.8, 0.99]), upwind discretisation: wall time of ctf_solve from psi = 0 to a float64
+    relative residual of 1e-6 for plain float64 multigrid, float32 cycles + float64 refinement,
+    and the same with the learned coarse-grid correction (trained here, seeded, on 32^2 .. 128^2
+    problems of the same physical cell size at the correction level)."""
+    import torch
+    from paper_2301_09991_amd import ctf, learned
+    from workloads import WORKLOADS, Workload, make_inputs
+    w = WORKLOADS["c4_learned"]
+    t0 = time.perf_counter()
+
+    def tw(N, seed, patch):
+        return Workload(f"train{seed}", N, w.L, w.p, 2, 1, patch, "iso", "box_quarter_phys", w.c_range, seed)
+    train = ([(tw(32, 4000 + k, 1), 0) for k in range(40)] + [(tw(64, 4100 + k, 2), 1) for k in range(20)]
+             + [(tw(128, 4200 + k, 4), 2) for k in range(10)])
+    F, T = learned.generate_samples(train, make_inputs)
+    theta, hist = learned.train(F, T, epochs=150, batch=16, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log(f"learned correction trained in {train_s:.1f} s ({F.shape[0]} samples, loss {hist[0]:.3g} -> {hist[-1]:.3g})")
+    inputs = make_inputs(w)
+    level = 5  # 32 x 32 correction grid, H = 1 (the training cell size)
+    out = {"workload": f"{w.name}: {w.N}x{w.N} nodes, L={w.L}, p={w.p}, {w.n_dir} ordinates, 1 group, "
+                       f"c in {list(w.c_range)}, upwind discretisation, rtol 1e-6",
+           "dof": w.dof, "train_seconds": train_s, "train_samples": int(F.shape[0]),
+           "train_loss_first_last": [hist[0], hist[-1]]}
+    for name, prec, use in (("plain_fp64", ctf.FP64, False), ("mixed", ctf.FP32_IR, False),
+                            ("learned_mixed", ctf.FP32_IR, True)):
+        prob = learned.make_problem(w, inputs, level, precision=prec)
+        if use:
+            prob.cnn_attach(theta)
+        psi = prob.zeros()
+        torch.cuda.synchronize()
+        info = prob.solve(psi, 1e-6, 2000)
+        out[name] = {"seconds": info["seconds"], "cycles": info["cycles"], "converged": info["converged"],
+                     "rel_residual": info["rel_residual"], "cnn_applied": info["cnn_applied"],
+                     "cnn_rejected": info["cnn_rejected"]}
+        log(f"time-to-1e-6 {name}: {info['seconds']:.3f} s, {info['cycles']} cycles")
+        del prob, psi
+        torch.cuda.empty_cache()
+    out["speedup_learned_mixed_vs_plain_fp64"] = out["plain_fp64"]["seconds"] / out["learned_mixed"]["seconds"]
+    out["speedup_mixed_vs_plain_fp64"] = out["plain_fp64"]["seconds"] / out["mixed"]["seconds"]
+    return out
+
+
+def batched(log):
+    """The batched workload: 64 problems with sizes drawn from {64, ..., 384}^2, p = 2, 512
+    ordinates, one group, upwind discretisation, float32 cycles + float64 refinement to 1e-6, all
+    solved by replays of one captured HIP graph; launch shapes autotuned per size."""
+    import tempfile
+    import torch
+    from paper_2301_09991_amd import ctf
+    from workloads import batch_workloads, make_inputs
+    ws = batch_workloads()
+    probs, psis, shapes = [], [], {}
+    with tempfile.TemporaryDirectory() as d:
+        cache = os.path.join(d, "autotune.json")
+        for w in ws:
+            st, ss, src = make_inputs(w)
+            cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=1, discretisation=ctf.UPWIND,
+                                     precision=ctf.FP32_IR)
+            p = ctf.Problem(cfg, st, ss, src)
+            shapes[w.N] = p.autotune(cache)
+            probs.append(p)
+            psis.append(p.zeros())
+    torch.cuda.synchronize()
+    dof = sum(w.dof for w in ws)
+    t0 = time.perf_counter()
+    ok, infos = ctf.solve_batch(probs, psis, 1e-6, 400, 2)
+    dt = time.perf_counter() - t0
+    cyc = [i["cycles"] for i in infos]
+    log(f"batched: {len(ws)} problems, {dof} DOF, converged={ok}, {dt:.3f} s")
+    return {"problems": len(ws), "dof": dof, "converged": ok, "seconds": dt,
+            "dof_updates_per_s": sum(w.dof * c for w, c in zip(ws, cyc)) / dt,
+            "cycles_min_max": [min(cyc), max(cyc)],
+            "max_rel_residual": max(i["rel_residual"] for i in infos),
+            "launch_shapes_by_n": {str(k): list(v) for k, v in sorted(shapes.items())}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +171,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default="c1_mixed")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the time-to-tolerance and batched measurements")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not part of it",
@@ -164,8 +246,15 @@ def main():
         "roofline": roof,
         "kernels": kernels,
     }
+    del prob, psi
+    torch.cuda.empty_cache()
+    log = lambda m: print(f"[bench] {m}", file=sys.stderr, flush=True)
+    if not args.no_extras:
+        line["time_to_tol"] = time_to_tolerance(log)
+        torch.cuda.empty_cache()
+        line["batched"] = batched(log)
     if not args.no_cpu_baseline:
-        print("[bench] timing the oracle on the host cores", file=sys.stderr, flush=True)
+        log("timing the oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line))
 
