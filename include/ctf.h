@@ -208,17 +208,22 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
                     int max_steps, int steps_per_graph, ctf_solve_info* infos);
 
 /* Launch shape of the finest-level kernels: rows per wavefront strip of the ConvFEM/PG kernels
- * (8..512) and the block size of the upwind correction sweeps (multiple of 64, <= 1024). */
-int ctf_set_launch_shape(ctf_problem* prob, int strip_h, int corr_block);
-int ctf_get_launch_shape(const ctf_problem* prob, int* strip_h, int* corr_block);
+ * (8..512), the block size of the upwind correction sweeps (multiple of 64, <= 1024), and for
+ * the non-linear PG whether the diffusivities are formed in the residual's own pass (pg_fused = 1)
+ * or in a pass of their own whose result the residual pass reads (0).  Results do not depend on
+ * the shape. */
+int ctf_set_launch_shape(ctf_problem* prob, int strip_h, int corr_block, int pg_fused);
+int ctf_get_launch_shape(const ctf_problem* prob, int* strip_h, int* corr_block, int* pg_fused);
 
 /* Autotuner: time the candidate launch shapes of the finest-level kernels on this problem's own
- * buffers (strip heights 8..128 for ConvFEM/PG, sweep blocks 64..1024), keep the fastest, and
+ * buffers (strip heights 8..128 and fused / two-pass for ConvFEM/PG, sweep blocks 64..1024),
+ * keep the fastest, and
  * record them in the JSON file cache_path under a key of (p, discretisation, precision, n, n_dir,
  * groups).  A problem whose key is already cached takes the cached shape without timing unless
  * force is set.  cache_path may be NULL (no file).  Synchronous; overwrites the problem's scratch
  * buffers (not psi).  The chosen shape is returned through strip_h / corr_block (may be NULL). */
-int ctf_autotune(ctf_problem* prob, const char* cache_path, int force, int* strip_h, int* corr_block);
+int ctf_autotune(ctf_problem* prob, const char* cache_path, int force, int* strip_h, int* corr_block,
+                 int* pg_fused);
 
 /* ||v||_W of a finest-level array (synchronous). */
 int ctf_norm(ctf_problem* prob, const double* v, double* out);

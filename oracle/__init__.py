@@ -7,7 +7,7 @@ use it.  It shares no code with the HIP library (``paper_2301_09991_amd``) and n
 Every function cites the passage of arXiv 2301.09991 (Phillips, Heaney, Chen, Buchan, Pain,
 "Solving the Discretised Boltzmann Transport Equations using Neural Networks") that it follows,
 by section / equation / appendix.  Where the paper is silent or garbled, the reading adopted is
-stated in the docstring (and listed in the design doc of the repository).
+stated in the docstring of the function that adopts it.
 
 Modules
 -------

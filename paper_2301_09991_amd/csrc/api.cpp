@@ -129,8 +129,9 @@ struct ctf_problem {
   PGParams pp{};
   int bc_vac = 0;
   int* active = nullptr;     // device flag read by every kernel (0: converged member of a batch)
-  int strip_h = 32;          // tuned launch shapes
+  int strip_h = 64;          // tuned launch shapes
   int corr_block = 256;
+  int pg_fused = 0;          // non-linear PG: diffusivities formed in the same pass (1) or stored (0)
   // learned coarse-grid correction
   int cnn_level = -1;
   bool cnn_on = false;
@@ -312,7 +313,7 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   if (frozen) {
     o.kx_in = P->kx;
     o.ky_in = P->ky;
-  } else {
+  } else if (k_float || !P->pg_fused) {
     o.kx_out = P->kx;
     o.ky_out = P->ky;
     if (k_float) {
@@ -326,14 +327,15 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   o.sign = sign;
   o.partial = (mode == 0 && want_norm) ? P->partial : nullptr;
   o.strip_h = P->strip_h;
+  int np = 0;
+  o.npartial = &np;
   {
     Timed t(P, CTF_T_PG64);
     CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, o, P->stream));
   }
   if (o.partial) {
     Timed t(P, CTF_T_NORM);
-    CTF_HIP(launch_sum_partials(P->partial, int(pg_partials(P->dims[0], P->strip_h)), P->scal, P->stream,
-                                P->active));
+    CTF_HIP(launch_sum_partials(P->partial, np, P->scal, P->stream, P->active));
   }
   return CTF_OK;
 }
@@ -466,12 +468,12 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   o.psi = x;
   o.E = P->E_f;
   o.nmomE = P->nmom;
-  if (c.discretisation == CTF_CONVFEM_PG && x != P->psi32_f) {
-    o.kx_out = P->kx_f;  // full-approximation form: diffusivities of the iterate itself
-    o.ky_out = P->ky_f;
-  } else {
-    o.kx_in = P->kx_f;   // frozen k, or the k of psi64 for b32 = A32(psi32) + rho64
+  if (c.discretisation != CTF_CONVFEM_PG) {
+    o.kx_in = P->kx_f;   // frozen k
     o.ky_in = P->ky_f;
+  } else if (!P->pg_fused) {
+    o.kx_out = P->kx_f;  // full-approximation form: k of x itself, stored then read
+    o.ky_out = P->ky_f;
   }
   o.out = out;
   o.rhs = P->r_f;
@@ -539,7 +541,7 @@ int outer_residual_async(ctf_problem* P, const double* psi) {
   if (rc) return rc;
   const int disc = P->cfg.discretisation;
   const size_t n = P->dof(0);
-  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, true);
+  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, false);
   rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true, false);
   if (rc) return rc;
   CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream, P->active));
@@ -565,8 +567,7 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   const size_t n = P->dof(0);
   const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
   if (fas) {
-    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64), with
-    // the diffusivities of psi64 left in kx_f, ky_f by the float64 residual
+    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64)
     CTF_HIP(launch_convert_d2f(psi, P->psi32_f, n, P->stream, P->active));
     CTF_HIP(launch_copy<float>(P->e_f, P->psi32_f, n, P->stream, P->active));
     int rc = inner_finest32(P, P->psi32_f, P->r_f, 0, -1.0f);
@@ -1203,31 +1204,37 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
   return status;
 }
 
-int ctf_set_launch_shape(ctf_problem* P, int strip_h, int corr_block) {
+int ctf_set_launch_shape(ctf_problem* P, int strip_h, int corr_block, int pg_fused) {
   if (!P) return fail(CTF_EINVAL, "null problem");
-  if (strip_h < 8 || strip_h > 512 || corr_block < 64 || corr_block > 1024 || corr_block % 64)
-    return fail(CTF_EINVAL, "strip_h in [8, 512], corr_block a multiple of 64 in [64, 1024]");
+  if (strip_h < 8 || strip_h > 512 || corr_block < 64 || corr_block > 1024 || corr_block % 64 ||
+      (pg_fused != 0 && pg_fused != 1))
+    return fail(CTF_EINVAL, "strip_h in [8, 512], corr_block a multiple of 64 in [64, 1024], pg_fused 0/1");
   P->strip_h = strip_h;
   P->corr_block = corr_block;
+  P->pg_fused = pg_fused;
   return CTF_OK;
 }
 
-int ctf_get_launch_shape(const ctf_problem* P, int* strip_h, int* corr_block) {
+int ctf_get_launch_shape(const ctf_problem* P, int* strip_h, int* corr_block, int* pg_fused) {
   if (!P) return fail(CTF_EINVAL, "null problem");
   if (strip_h) *strip_h = P->strip_h;
   if (corr_block) *corr_block = P->corr_block;
+  if (pg_fused) *pg_fused = P->pg_fused;
   return CTF_OK;
 }
 
-int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h, int* corr_block) {
+int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h, int* corr_block,
+                 int* pg_fused) {
   if (!P) return fail(CTF_EINVAL, "null problem");
   const std::string key = tune_key(P);
   std::map<std::string, std::string> cache;
   if (cache_path) cache = read_cache(cache_path);
   auto it = cache.find(key);
   double a = 0, b = 0;
+  double f = 0;
   if (!force && it != cache.end() && field(it->second, "strip_h", &a) && field(it->second, "corr_block", &b)) {
-    int rc = ctf_set_launch_shape(P, int(a), int(b));
+    (void)field(it->second, "pg_fused", &f);
+    int rc = ctf_set_launch_shape(P, int(a), int(b), int(f));
     if (rc) return rc;
   } else {
     const ctf_config& c = P->cfg;
@@ -1250,17 +1257,25 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
     P->timing = false;
     double best_pg = 1e30, best_corr = 1e30;
     int best_h = P->strip_h, best_b = P->corr_block;
+    int best_f = P->pg_fused;
     if (c.discretisation != CTF_UPWIND) {
+      for (int fz = 0; fz < (c.discretisation == CTF_CONVFEM_PG ? 2 : 1); ++fz)
       for (int h : {8, 16, 32, 64, 128}) {
         P->strip_h = h;
+        P->pg_fused = fz;
         double ms = 0.0;
         if (P->mixed()) {
           PGLaunch<float> o;
           o.psi = P->ea_f[0];
           o.E = P->E_f;
           o.nmomE = P->nmom;
-          o.kx_in = P->kx_f ? P->kx_f : P->ea_f[0];
-          o.ky_in = P->ky_f ? P->ky_f : P->ea_f[0];
+          if (c.discretisation == CTF_CONVFEM_PG_FROZEN_K) {
+            o.kx_in = P->kx_f;
+            o.ky_in = P->ky_f;
+          } else if (!fz) {
+            o.kx_out = P->kx_f;
+            o.ky_out = P->ky_f;
+          }
           o.out = P->eb_f[0];
           o.rhs = P->r_f;
           o.mode = 1;
@@ -1274,6 +1289,7 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
         if (ms < best_pg) {
           best_pg = ms;
           best_h = h;
+          best_f = fz;
         }
       }
     }
@@ -1295,10 +1311,12 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
     P->timing = saved_timing;
     P->strip_h = best_h;
     P->corr_block = best_b;
+    P->pg_fused = best_f;
     if (rc) return rc;
     if (cache_path) {
       std::ostringstream e;
-      e << "{\"strip_h\": " << best_h << ", \"corr_block\": " << best_b << ", \"pg_ms\": "
+      e << "{\"strip_h\": " << best_h << ", \"corr_block\": " << best_b << ", \"pg_fused\": " << best_f
+        << ", \"pg_ms\": "
         << (best_pg < 1e30 ? best_pg : 0.0) << ", \"corr_ms\": " << best_corr << "}";
       cache[key] = e.str();
       std::ofstream outf(cache_path, std::ios::trunc);
@@ -1311,6 +1329,7 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
   }
   if (strip_h) *strip_h = P->strip_h;
   if (corr_block) *corr_block = P->corr_block;
+  if (pg_fused) *pg_fused = P->pg_fused;
   return CTF_OK;
 }
 

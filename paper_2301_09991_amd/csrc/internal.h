@@ -87,8 +87,9 @@ hipError_t launch_emission(const LevelDims& d, const T* phi, const T* sigma_s, i
 // Finest ConvFEM Petrov-Galerkin operator.
 //   mode 0: out = sign * rho (out and / or out_f; partial: per-block sum of w_n h^2 out^2)
 //   mode 1: out = psi + rho / (beta d)
-//   kx_in, ky_in != null: these diffusivities (frozen); else k is computed from psi into
-//   kx_out, ky_out (required), plus float copies in kx_out_f, ky_out_f if non-null
+//   kx_in, ky_in != null: these diffusivities (frozen); else k is computed from psi: on the fly
+//   (fused kernel) when no k output is requested, or first into kx_out, ky_out (plus float
+//   copies in kx_out_f, ky_out_f if non-null)
 //   rhs != null: a per-DOF term added to the emission (right-hand side of a correction equation)
 template <typename T>
 struct PGLaunch {
@@ -108,6 +109,7 @@ struct PGLaunch {
   int mode = 0;
   T sign = T(1);
   int strip_h = 32;   // rows per wavefront strip (tunable)
+  int* npartial = nullptr;  // receives the number of per-block partial sums written (mode 0)
 };
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,

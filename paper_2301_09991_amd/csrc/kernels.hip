@@ -486,6 +486,198 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   }
 }
 
+// Fused non-linear form: the diffusivities are formed in the same pass and never stored.
+// A wavefront owns 64 columns, lane l at column xs - 2P + l, and writes the 64 - 4P columns
+// xs .. xs + 63 - 4P; rows stream through a four-stage pipeline (row r loaded at step r):
+//   A  Psi_x, Psi_y of row r - P          (x-pass on the psi row, y-pass over registers)
+//   B  R_x, R_y and k_x, k_y of row r - 2P (x-pass on the Psi row, y-pass over registers)
+//   C  x-passes of psi, k psi, k for row s = r - 3P (psi and k rows from LDS rings; the k
+//      halo copies the nearest interior row / column)
+//   D  output row r - 4P (y-passes over registers)
+template <int P, typename T>
+__global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
+  if (idle(a.L.dims.active)) return;
+  constexpr int W = 2 * P + 1;
+  constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
+  constexpr int PR = 3 * P + 1;         // psi rows kept (rows r - 3P .. r)
+  constexpr int KR = P + 1;             // k rows kept
+  constexpr int OW = kStripW - 4 * P;   // columns written per strip
+  __shared__ T s_psi[PR][RW];
+  __shared__ T s_gx[kStripW];
+  __shared__ T s_gy[kStripW];
+  __shared__ T s_kx[KR][kStripW];
+  __shared__ T s_ky[KR][kStripW];
+  const int n = a.L.dims.n;
+  const int lane = threadIdx.x;
+  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
+  const int c0 = xs - 2 * P;            // column of lane 0
+  const int dir = blockIdx.y, g = blockIdx.z;
+  const size_t ncell = size_t(n) * n;
+  const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
+  const T mu = a.L.mu[dir], nu = a.L.nu[dir];
+  const T h = T(a.L.dims.h);
+  const T* __restrict__ psi = a.psi + base;
+  T cm[W], cd[W], ck[W];
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    cm[t] = a.st.m[t];
+    cd[t] = a.st.d[t];
+    ck[t] = a.st.k[t];
+  }
+  T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
+  T cgx[P + 1] = {}, cgy[P + 1] = {};
+  T ogx[3 * P + 1] = {}, ogy[3 * P + 1] = {};
+  T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
+  T cpsi[P + 1] = {}, ckx[P + 1] = {}, cky[P + 1] = {};
+  // psi row loads: lane l -> column c0 - P + l; lanes < 2P also column c0 - P + 64 + l
+  const int lc0 = c0 - P + lane, lc1 = lc0 + kStripW;
+  const int cc0 = clampi(lc0, 0, n - 1), cc1 = clampi(lc1, 0, n - 1);
+  const bool zx0 = (lc0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (lc0 >= n && (a.bc_vac & 2) && mu < T(0));
+  const bool zx1 = (lc1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (lc1 >= n && (a.bc_vac & 2) && mu < T(0));
+  const int col = c0 + lane;
+  const bool writer = lane >= 2 * P && lane < kStripW - 2 * P && col < n;
+  const bool kvalid = lane >= P && lane < kStripW - P;
+  // lane holding the k of the clamped column of lane + u - P (for the k halo copy)
+  const int yend = min(y0 + a.strip_h, n);
+  const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
+  const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
+  double acc = 0.0;
+  T p0, p1 = 0;
+  auto load_row = [&](int r, T& vp0, T& vp1) {
+    const int cr = clampi(r, 0, n - 1);
+    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+    const size_t ro = size_t(cr) * n;
+    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
+    if (lane < 2 * P) vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+  };
+  const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
+  load_row(rbeg, p0, p1);
+  for (int r = rbeg; r < rend; ++r) {
+    const int slot = ((r % PR) + PR) % PR;
+    __syncthreads();                        // stage C of the previous step read the slot reused here
+    s_psi[slot][lane] = p0;
+    if (lane < 2 * P) s_psi[slot][kStripW + lane] = p1;
+    if (r + 1 < rend) load_row(r + 1, p0, p1);
+    __syncthreads();
+    // A: Psi of row r - P
+    {
+      T xd = 0, xm = 0;
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        const T v = s_psi[slot][lane + u];
+        xd += cd[u] * v;
+        xm += cm[u] * v;
+      }
+      push(wXd, xd);
+      push(wXm, xm);
+      const T gx = ypass(wXd, cm), gy = ypass(wXm, cd);
+      s_gx[lane] = gx;
+      s_gy[lane] = gy;
+      push(cgx, gx);
+      push(cgy, gy);
+      push(ogx, gx);
+      push(ogy, gy);
+    }
+    __syncthreads();
+    // B: k of row r - 2P
+    {
+      T mx = 0, my = 0;
+      if (kvalid) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          mx += cm[u] * s_gx[lane - P + u];
+          my += cm[u] * s_gy[lane - P + u];
+        }
+      }
+      push(wMx, mx);
+      push(wMy, my);
+      const int rk = r - 2 * P;
+      if (rk >= 0 && rk < n) {
+        const T px = cgx[0], py = cgy[0];
+        const T rx = ar * mu * (ypass(wMx, cm) - px);
+        const T ry = ar * nu * (ypass(wMy, cm) - py);
+        const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
+                          aksq * rx * rx * h / (eps + tabs(mu) * px * px));
+        const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
+                          aksq * ry * ry * h / (eps + tabs(nu) * py * py));
+        s_kx[rk % KR][lane] = kx;
+        s_ky[rk % KR][lane] = ky;
+      }
+    }
+    __syncthreads();
+    // C: x-passes of row s = r - 3P (k of the clamped row and columns)
+    {
+      const int srow = r - 3 * P;
+      const int sslot = ((srow % PR) + PR) % PR;
+      const int kslot = clampi(srow, 0, n - 1) % KR;
+      T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0, pc = 0, kxc = 0, kyc = 0;
+      if (lane >= P && lane < kStripW - P) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          const int kl = clampi(col + u - P, 0, n - 1) - c0;   // lane of the clamped column
+          const T v = s_psi[sslot][lane + u];
+          const T kv = s_kx[kslot][kl], qv = s_ky[kslot][kl];
+          a1x += ck[u] * v;
+          a2x += ck[u] * (kv * v);
+          a3x += ck[u] * kv;
+          a1y += cm[u] * v;
+          a2y += cm[u] * (qv * v);
+          a3y += cm[u] * qv;
+        }
+        pc = s_psi[sslot][lane + P];
+        const int kc = clampi(col, 0, n - 1) - c0;
+        kxc = s_kx[kslot][kc];
+        kyc = s_ky[kslot][kc];
+      }
+      push(wA1x, a1x);
+      push(wA2x, a2x);
+      push(wA3x, a3x);
+      push(wA1y, a1y);
+      push(wA2y, a2y);
+      push(wA3y, a3y);
+      push(cpsi, pc);
+      push(ckx, kxc);
+      push(cky, kyc);
+    }
+    // D: output row r - 4P
+    const int o = r - 4 * P;
+    if (o >= y0 && writer) {
+      const T px = ogx[0], py = ogy[0];
+      const T psc = cpsi[0];
+      const T dx = ckx[0] * ypass(wA1x, cm) + ypass(wA2x, cm) - psc * ypass(wA3x, cm);
+      const T dy = cky[0] * ypass(wA1y, ck) + ypass(wA2y, ck) - psc * ypass(wA3y, ck);
+      const size_t cell = size_t(o) * n + col;
+      const size_t eb = size_t(g) * a.nmomE * ncell + cell;
+      T q = a.E[eb];
+      if (a.nmomE > 1) q += mu * a.E[eb + ncell] + nu * a.E[eb + 2 * ncell];
+      if (a.rhs) q += a.rhs[base + cell];
+      const T sig = a.L.sigma_t[size_t(g) * ncell + cell];
+      const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
+      if (a.mode == 0) {
+        const T val = a.sign * rho;
+        if (a.out) a.out[base + cell] = val;
+        if (a.out_f) a.out_f[base + cell] = float(val);
+        acc += double(val) * double(val);
+      } else {
+        a.out[base + cell] = psc + rho / (diag + a.beta * sig);
+      }
+    }
+  }
+  if (a.partial) {
+    __shared__ double red[kStripW];
+    red[lane] = acc;
+    __syncthreads();
+    for (int st = kStripW / 2; st > 0; st >>= 1) {
+      if (lane < st) red[lane] += red[lane + st];
+      __syncthreads();
+    }
+    if (lane == 0) {
+      const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
+      a.partial[b] = red[0] * double(a.L.w[dir]) * a.L.dims.h * a.L.dims.h;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // finest upwind operator (eq. discretised_hfm): rho = q - A_up psi - sigma_t psi
 template <typename T>
@@ -769,6 +961,23 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.sign = o.sign;
   a.strip_h = o.strip_h;
   const int n = L.dims.n;
+  if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
+    // fused: the diffusivities of psi are formed on the fly
+    a.out = o.out;
+    a.out_f = o.out_f;
+    a.partial = o.partial;
+    const int ow = kStripW - 4 * p;
+    a.ntx = (n + ow - 1) / ow;
+    const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
+    if (o.npartial) *o.npartial = int(grid.x * grid.y * grid.z);
+    switch (p) {
+      case 1: hipLaunchKernelGGL((k_pg_fused<1, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 2: hipLaunchKernelGGL((k_pg_fused<2, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 3: hipLaunchKernelGGL((k_pg_fused<3, T>), grid, dim3(kStripW), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   if (!o.kx_in) {
     // diffusivities of psi first (into kx_out / ky_out, and / or their float copies)
     if (!o.kx_out) return hipErrorInvalidValue;
@@ -798,6 +1007,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.partial = o.partial;
   a.ntx = (n + kStripW - 1) / kStripW;
   const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
+  if (o.npartial) *o.npartial = int(grid.x * grid.y * grid.z);
   switch (p) {
     case 1: hipLaunchKernelGGL((k_pg_stream<1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_pg_stream<2, T>), grid, dim3(kStripW), 0, s, a); break;
@@ -808,7 +1018,9 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
 }
 
 size_t pg_partials(const LevelDims& d, int strip_h) {
-  const size_t strips = size_t((d.n + kStripW - 1) / kStripW) * ((d.n + strip_h - 1) / strip_h);
+  // the fused kernel's strips are the narrowest (64 - 4P columns, P <= 3)
+  const int ow = kStripW - 4 * kMaxP;
+  const size_t strips = size_t((d.n + ow - 1) / ow) * ((d.n + strip_h - 1) / strip_h);
   return strips * d.nd * d.G;
 }
 

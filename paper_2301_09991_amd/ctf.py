@@ -94,9 +94,9 @@ def load():
         "ctf_cnn_enable": (I, [P, I]),
         "ctf_cnn_sample": (I, [P, P, P, P, P, ctypes.POINTER(D)]),
         "ctf_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), D, I, I, ctypes.POINTER(SolveInfo)]),
-        "ctf_set_launch_shape": (I, [P, I, I]),
-        "ctf_get_launch_shape": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I)]),
-        "ctf_autotune": (I, [P, ctypes.c_char_p, I, ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ctf_set_launch_shape": (I, [P, I, I, I]),
+        "ctf_get_launch_shape": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
+        "ctf_autotune": (I, [P, ctypes.c_char_p, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "ctf_freeze_k": (I, [P, P, P, P]),
         "ctf_smooth": (I, [P, I, I, P, P, I]),
         "ctf_restrict": (I, [P, I, P, P]),
@@ -344,19 +344,20 @@ class Problem:
         return out
 
     # -- launch shapes
-    def set_launch_shape(self, strip_h, corr_block):
-        _check(self.lib.ctf_set_launch_shape(self.handle, strip_h, corr_block))
+    def set_launch_shape(self, strip_h, corr_block, pg_fused=0):
+        _check(self.lib.ctf_set_launch_shape(self.handle, strip_h, corr_block, int(pg_fused)))
 
     def launch_shape(self):
-        a, b = ctypes.c_int(), ctypes.c_int()
-        _check(self.lib.ctf_get_launch_shape(self.handle, ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        a, b, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(self.lib.ctf_get_launch_shape(self.handle, ctypes.byref(a), ctypes.byref(b), ctypes.byref(f)))
+        return a.value, b.value, f.value
 
     def autotune(self, cache_path=None, force=False):
-        a, b = ctypes.c_int(), ctypes.c_int()
+        a, b, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         path = cache_path.encode() if cache_path else None
-        _check(self.lib.ctf_autotune(self.handle, path, int(force), ctypes.byref(a), ctypes.byref(b)))
-        return a.value, b.value
+        _check(self.lib.ctf_autotune(self.handle, path, int(force), ctypes.byref(a), ctypes.byref(b),
+                                     ctypes.byref(f)))
+        return a.value, b.value, f.value
 
     # -- learned coarse-grid correction
     def cnn_attach(self, params):

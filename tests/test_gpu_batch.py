@@ -66,8 +66,8 @@ def test_results_do_not_depend_on_launch_shape(disc, precision):
     if disc == 2:
         gp.freeze_k(psi)
     outs = []
-    for strip_h, block in ((32, 256), (8, 64), (128, 1024)):
-        gp.set_launch_shape(strip_h, block)
+    for strip_h, block, fused in ((32, 256, 0), (8, 64, 1), (128, 1024, 1), (16, 512, 0)):
+        gp.set_launch_shape(strip_h, block, fused)
         out = gp.empty()
         gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
         x = psi.clone()
@@ -84,11 +84,11 @@ def test_autotune_picks_and_caches_a_shape():
     prob = _problem(w, ctf.FP32_IR, disc=ctf.CONVFEM_PG)
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.json")
-        h, b = prob.autotune(path)
-        assert h in (8, 16, 32, 64, 128) and b in (64, 128, 256, 512, 1024)
+        h, b, f = prob.autotune(path)
+        assert h in (8, 16, 32, 64, 128) and b in (64, 128, 256, 512, 1024) and f in (0, 1)
         assert os.path.exists(path)
         text = open(path).read()
         assert '"strip_h": %d' % h in text
         other = _problem(w, ctf.FP32_IR, disc=ctf.CONVFEM_PG)
-        assert other.autotune(path) == (h, b)
-        assert other.launch_shape() == (h, b)
+        assert other.autotune(path) == (h, b, f)
+        assert other.launch_shape() == (h, b, f)
