@@ -287,6 +287,8 @@ enum {
   CTF_T_NORM,
   CTF_T_MOMENTS_MFMA,  /* bf16 MFMA moment contraction */
   CTF_T_CNN,           /* learned correction: features, network, application */
+  CTF_T_PGK64,         /* stored non-linear PG diffusivities (their own pass), float64 */
+  CTF_T_PGK32,         /* same, float32 */
   CTF_T_COUNT
 };
 int ctf_timing_enable(ctf_problem* prob, int on, int capacity);

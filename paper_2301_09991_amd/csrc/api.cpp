@@ -284,6 +284,25 @@ int emission64(ctf_problem* P, const double* psi, bool with_source) {
   return CTF_OK;
 }
 
+// One PG launch with its timers: when the diffusivities are stored (kx_out without kx_in) their pass
+// is timed as a class of its own, then the residual pass reads them back.
+template <typename T>
+int run_pg(ctf_problem* P, int cls, int cls_k, const LevelData<T>& L, const Stencils<T>& st, PGLaunch<T> o) {
+  if (!o.kx_in && o.kx_out) {
+    {
+      Timed t(P, cls_k);
+      CTF_HIP(launch_pg_diffusivity<T>(P->cfg.p, L, st, P->pp, o, P->stream));
+    }
+    o.kx_in = o.kx_out;
+    o.ky_in = o.ky_out;
+    o.kx_out = o.ky_out = nullptr;
+    o.kx_out_f = o.ky_out_f = nullptr;
+  }
+  Timed t(P, cls);
+  CTF_HIP(launch_pg<T>(P->cfg.p, L, st, P->pp, o, P->stream));
+  return CTF_OK;
+}
+
 // Finest operator with the emission already in E.
 //   mode 0: out = sign * rho(psi) (out and / or out_f), with the squared weighted norm summed into
 //           P->scal[0] when want_norm; mode 1: out = psi + rho / (beta d).
@@ -329,10 +348,8 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   o.strip_h = P->strip_h;
   int np = 0;
   o.npartial = &np;
-  {
-    Timed t(P, CTF_T_PG64);
-    CTF_HIP(launch_pg<double>(c.p, P->ld(0), P->st_d, P->pp, o, P->stream));
-  }
+  int rc = run_pg<double>(P, CTF_T_PG64, CTF_T_PGK64, P->ld(0), P->st_d, o);
+  if (rc) return rc;
   if (o.partial) {
     Timed t(P, CTF_T_NORM);
     CTF_HIP(launch_sum_partials(P->partial, np, P->scal, P->stream, P->active));
@@ -480,9 +497,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   o.mode = mode;
   o.sign = sign;
   o.strip_h = P->strip_h;
-  Timed t(P, CTF_T_PG32);
-  CTF_HIP(launch_pg<float>(c.p, P->lf(0), P->st_f, P->pp, o, P->stream));
-  return CTF_OK;
+  return run_pg<float>(P, CTF_T_PG32, CTF_T_PGK32, P->lf(0), P->st_f, o);
 }
 
 // one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0)
@@ -902,11 +917,10 @@ int ctf_freeze_k(ctf_problem* P, const double* psi, double* kx, double* ky) {
   o.nmomE = P->nmom;
   o.kx_out = P->kx;
   o.ky_out = P->ky;
-  o.out = P->psi_tmp;
   o.strip_h = P->strip_h;
   {
-    Timed t(P, CTF_T_PG64);
-    CTF_HIP(launch_pg<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, o, P->stream));
+    Timed t(P, CTF_T_PGK64);
+    CTF_HIP(launch_pg_diffusivity<double>(P->cfg.p, P->ld(0), P->st_d, P->pp, o, P->stream));
   }
   P->k_held = true;
   const size_t bytes = P->dof(0) * sizeof(double);

@@ -111,9 +111,16 @@ struct PGLaunch {
   int strip_h = 32;   // rows per wavefront strip (tunable)
   int* npartial = nullptr;  // receives the number of per-block partial sums written (mode 0)
 };
+// Residual / sweep of the ConvFEM-PG operator.  With neither kx_in nor kx_out the non-linear
+// diffusivities are formed inside the one pass; with kx_out (and no kx_in) they are formed by
+// launch_pg_diffusivity first and read back; with kx_in they are taken as given.
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
                      const PGLaunch<T>& o, hipStream_t s);
+// The diffusivities of o.psi alone, into o.kx_out / o.ky_out (and o.kx_out_f / o.ky_out_f).
+template <typename T>
+hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
+                                 const PGLaunch<T>& o, hipStream_t s);
 // number of per-block partial sums a mode-0 launch_pg writes with this strip height
 size_t pg_partials(const LevelDims& d, int strip_h);
 

@@ -254,6 +254,17 @@ __device__ __forceinline__ T ypass(const T (&w)[W], const T* c) {
   return s;
 }
 
+// y-pass over a window filled in rotation: slot t holds the newest row, slot (t + 1) % W the
+// oldest.  Called with t a constant of a fully unrolled loop, so every index is static and the
+// window stays in registers without the moves of push().
+template <typename T, int W>
+__device__ __forceinline__ T yrot(const T (&w)[W], const T* c, int t) {
+  T s = 0;
+#pragma unroll
+  for (int u = 0; u < W; ++u) s += c[u] * w[(t + 1 + u) % W];
+  return s;
+}
+
 // Residual with given diffusivities (k_x, k_y read with a copied halo):
 //   rho = rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
 //   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
@@ -262,9 +273,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;
-  __shared__ T s_psi[RW];
-  __shared__ T s_kx[RW];
-  __shared__ T s_ky[RW];
+  constexpr int D = P + 2;   // LDS ring of input rows: the current row and the P rows above it
+  __shared__ T s_psi[D][RW];
+  __shared__ T s_kx[D][RW];
+  __shared__ T s_ky[D][RW];
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
@@ -283,8 +295,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
     cd[t] = a.st.d[t];
     ck[t] = a.st.k[t];
   }
+  // x-pass results of the last W rows, slot = (row - first row) % W
   T wXd[W] = {}, wXm[W] = {}, wXk[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA2y[W] = {}, wA3y[W] = {};
-  T cpsi[P + 1] = {}, ckx[P + 1] = {}, cky[P + 1] = {};
   const int gi = x0 + lane;
   const int c0 = x0 - P + lane, c1 = c0 + kStripW;
   const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
@@ -293,77 +305,98 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   const int yend = min(y0 + a.strip_h, n);
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
-  // row values are loaded one row ahead so that the loads overlap the filtering of a row
-  T p0, k0, q0, p1 = 0, k1 = 0, q1 = 0;
-  auto load_row = [&](int r, T& vp0, T& vk0, T& vq0, T& vp1, T& vk1, T& vq1) {
-    const int cr = clampi(r, 0, n - 1);
-    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-    const size_t ro = size_t(cr) * n;
-    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
-    vk0 = kxin[ro + cc0];
-    vq0 = kyin[ro + cc0];
-    if (lane < 2 * P) {
-      vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
-      vk1 = kxin[ro + cc1];
-      vq1 = kyin[ro + cc1];
-    }
+  // Row values are loaded one row ahead so that the loads overlap the filtering of a row; so are
+  // the per-cell values of the output row they complete (emission, rhs, sigma_t).  Every load is
+  // unconditional, from a clamped (in-bounds) address, and the halo rule and unused values are
+  // applied at the use: a load under a branch would make the wave wait for it at the join.
+  T p0, k0, q0, p1, k1, q1;
+  T fe0, fe1, fe2, frh, fs;   // emission moments, rhs, sigma_t of output row r - P
+  const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
+  const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
+  const T* __restrict__ E1g = p1mom ? Eg + ncell : Eg;
+  const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
+  const T* __restrict__ sigg = a.L.sigma_t + size_t(g) * ncell;
+  const T* __restrict__ rhsp = has_rhs ? a.rhs + base : Eg;
+  const int gic = min(gi, n - 1);
+  auto load_row = [&](int r) {
+    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    p0 = psi[ro + cc0];
+    k0 = kxin[ro + cc0];
+    q0 = kyin[ro + cc0];
+    p1 = psi[ro + cc1];
+    k1 = kxin[ro + cc1];
+    q1 = kyin[ro + cc1];
+    const size_t cell = size_t(clampi(r - P, 0, n - 1)) * n + gic;
+    fe0 = Eg[cell];
+    fe1 = E1g[cell];
+    fe2 = E2g[cell];
+    frh = rhsp[cell];
+    fs = sigg[cell];
   };
-  load_row(y0 - P, p0, k0, q0, p1, k1, q1);
-  for (int r = y0 - P; r < yend + P; ++r) {
-    s_psi[lane] = p0;
-    s_kx[lane] = k0;
-    s_ky[lane] = q0;
-    if (lane < 2 * P) {
-      s_psi[kStripW + lane] = p1;
-      s_kx[kStripW + lane] = k1;
-      s_ky[kStripW + lane] = q1;
-    }
-    if (r + 1 < yend + P) load_row(r + 1, p0, k0, q0, p1, k1, q1);
-    __syncthreads();
-    T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
+  const int rbeg = y0 - P, rend = yend + P;
+  load_row(rbeg);
+  int ring = 0;   // ring slot of the current row
+  for (int r0 = rbeg; r0 < rend; r0 += W) {
 #pragma unroll
-    for (int u = 0; u < W; ++u) {
-      const T v = s_psi[lane + u], kv = s_kx[lane + u], qv = s_ky[lane + u];
-      xd += cd[u] * v;
-      xm += cm[u] * v;
-      xk += ck[u] * v;
-      a2x += ck[u] * (kv * v);
-      a3x += ck[u] * kv;
-      a2y += cm[u] * (qv * v);
-      a3y += cm[u] * qv;
-    }
-    push(cpsi, s_psi[lane + P]);
-    push(ckx, s_kx[lane + P]);
-    push(cky, s_ky[lane + P]);
-    __syncthreads();
-    push(wXd, xd);
-    push(wXm, xm);
-    push(wXk, xk);
-    push(wA2x, a2x);
-    push(wA3x, a3x);
-    push(wA2y, a2y);
-    push(wA3y, a3y);
-    const int o = r - P;
-    if (o >= y0 && gi < n) {
-      const T px = ypass(wXd, cm), py = ypass(wXm, cd);
-      const T pc = cpsi[0];
-      const T dx = ckx[0] * ypass(wXk, cm) + ypass(wA2x, cm) - pc * ypass(wA3x, cm);
-      const T dy = cky[0] * ypass(wXm, ck) + ypass(wA2y, ck) - pc * ypass(wA3y, ck);
-      const size_t cell = size_t(o) * n + gi;
-      const size_t eb = size_t(g) * a.nmomE * ncell + cell;
-      T q = a.E[eb];
-      if (a.nmomE > 1) q += mu * a.E[eb + ncell] + nu * a.E[eb + 2 * ncell];
-      if (a.rhs) q += a.rhs[base + cell];
-      const T sig = a.L.sigma_t[size_t(g) * ncell + cell];
-      const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
-      if (a.mode == 0) {
-        const T val = a.sign * rho;
-        if (a.out) a.out[base + cell] = val;
-        if (a.out_f) a.out_f[base + cell] = float(val);
-        acc += double(val) * double(val);
-      } else {
-        a.out[base + cell] = pc + rho / (diag + a.beta * sig);
+    for (int t = 0; t < W; ++t) {
+      const int r = r0 + t;
+      if (r >= rend) break;
+      T* const rp = s_psi[ring];
+      T* const rk = s_kx[ring];
+      T* const rq = s_ky[ring];
+      const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+      rp[lane] = (zy || zx0) ? T(0) : p0;
+      rk[lane] = k0;
+      rq[lane] = q0;
+      if (lane < 2 * P) {
+        rp[kStripW + lane] = (zy || zx1) ? T(0) : p1;
+        rk[kStripW + lane] = k1;
+        rq[kStripW + lane] = q1;
       }
+      const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+      load_row(r + 1);   // past the last row this reloads a clamped row, unused
+      __syncthreads();
+      T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        const T v = rp[lane + u], kv = rk[lane + u], qv = rq[lane + u];
+        xd += cd[u] * v;
+        xm += cm[u] * v;
+        xk += ck[u] * v;
+        a2x += ck[u] * (kv * v);
+        a3x += ck[u] * kv;
+        a2y += cm[u] * (qv * v);
+        a3y += cm[u] * qv;
+      }
+      wXd[t] = xd;
+      wXm[t] = xm;
+      wXk[t] = xk;
+      wA2x[t] = a2x;
+      wA3x[t] = a3x;
+      wA2y[t] = a2y;
+      wA3y[t] = a3y;
+      const int o = r - P;
+      if (o >= y0 && gi < n) {
+        const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of row o
+        const T pc = s_psi[cs][lane + P], kxc = s_kx[cs][lane + P], kyc = s_ky[cs][lane + P];
+        const T px = yrot(wXd, cm, t), py = yrot(wXm, cd, t);
+        const T dx = kxc * yrot(wXk, cm, t) + yrot(wA2x, cm, t) - pc * yrot(wA3x, cm, t);
+        const T dy = kyc * yrot(wXm, ck, t) + yrot(wA2y, ck, t) - pc * yrot(wA3y, ck, t);
+        const size_t cell = size_t(o) * n + gi;
+        T q = e0;
+        if (p1mom) q += mu * e1 + nu * e2;
+        if (has_rhs) q += rh;
+        const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
+        if (a.mode == 0) {
+          const T val = a.sign * rho;
+          if (a.out) a.out[base + cell] = val;
+          if (a.out_f) a.out_f[base + cell] = float(val);
+          acc += double(val) * double(val);
+        } else {
+          a.out[base + cell] = pc + rho / (diag + a.beta * sig);
+        }
+      }
+      ring = ring + 1 == D ? 0 : ring + 1;
     }
   }
   if (a.partial) {
@@ -392,9 +425,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
+  constexpr int D = P + 2;              // LDS ring of Psi rows: the newest and the P rows above it
   __shared__ T s_psi[RW];
-  __shared__ T s_gx[kStripW];
-  __shared__ T s_gy[kStripW];
+  __shared__ T s_gx[D][kStripW];
+  __shared__ T s_gy[D][kStripW];
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
@@ -411,8 +445,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
     cm[t] = a.st.m[t];
     cd[t] = a.st.d[t];
   }
+  // rotating windows (slot = step % W): x-passes of psi rows, x-passes of Psi rows
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
-  T cgx[P + 1] = {}, cgy[P + 1] = {};
   const int c0 = x0 - P + lane, c1 = c0 + kStripW;
   const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
   const bool zx0 = (c0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c0 >= n && (a.bc_vac & 2) && mu < T(0));
@@ -421,67 +455,73 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   const bool writer = lane >= P && lane < kStripW - P && gi < n && gi < xs + OW;
   const int yend = min(y0 + a.strip_h, n);
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
-  T p0, p1 = 0;
-  auto load_row = [&](int r, T& vp0, T& vp1) {
-    const int cr = clampi(r, 0, n - 1);
-    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-    const size_t ro = size_t(cr) * n;
-    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
-    if (lane < 2 * P) {
-      vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
-    }
+  // rows are loaded one ahead, unconditionally from clamped addresses (the halo rule is applied
+  // when the row is written to LDS), so that no join waits for a load in flight
+  T p0, p1;
+  auto load_row = [&](int r) {
+    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    p0 = psi[ro + cc0];
+    p1 = psi[ro + cc1];
   };
-  load_row(y0 - 2 * P, p0, p1);
-  for (int r = y0 - 2 * P; r < yend + 2 * P; ++r) {
-    s_psi[lane] = p0;
-    if (lane < 2 * P) s_psi[kStripW + lane] = p1;
-    if (r + 1 < yend + 2 * P) load_row(r + 1, p0, p1);
-    __syncthreads();
-    T xd = 0, xm = 0;
+  const int rbeg = y0 - 2 * P, rend = yend + 2 * P;
+  load_row(rbeg);
+  int ring = 0;   // ring slot of the Psi row formed at this step
+  for (int r0 = rbeg; r0 < rend; r0 += W) {
 #pragma unroll
-    for (int u = 0; u < W; ++u) {
-      const T v = s_psi[lane + u];
-      xd += cd[u] * v;
-      xm += cm[u] * v;
-    }
-    push(wXd, xd);
-    push(wXm, xm);
-    // Psi on row r - P (valid once the window is full)
-    const T gx = ypass(wXd, cm), gy = ypass(wXm, cd);
-    s_gx[lane] = gx;
-    s_gy[lane] = gy;
-    push(cgx, gx);
-    push(cgy, gy);
-    __syncthreads();
-    T mx = 0, my = 0;
-    if (lane >= P && lane < kStripW - P) {
+    for (int t = 0; t < W; ++t) {
+      const int r = r0 + t;
+      if (r >= rend) break;
+      const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+      s_psi[lane] = (zy || zx0) ? T(0) : p0;
+      if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : p1;
+      load_row(r + 1);   // past the last row this reloads a clamped row, unused
+      __syncthreads();
+      T xd = 0, xm = 0;
 #pragma unroll
       for (int u = 0; u < W; ++u) {
-        mx += cm[u] * s_gx[lane - P + u];
-        my += cm[u] * s_gy[lane - P + u];
+        const T v = s_psi[lane + u];
+        xd += cd[u] * v;
+        xm += cm[u] * v;
       }
-    }
-    push(wMx, mx);
-    push(wMy, my);
-    __syncthreads();
-    const int o = r - 2 * P;
-    if (o >= y0 && writer) {
-      const T px = cgx[0], py = cgy[0];
-      const T rx = ar * mu * (ypass(wMx, cm) - px);
-      const T ry = ar * nu * (ypass(wMy, cm) - py);
-      const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
-                        aksq * rx * rx * h / (eps + tabs(mu) * px * px));
-      const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
-                        aksq * ry * ry * h / (eps + tabs(nu) * py * py));
-      const size_t cell = size_t(o) * n + gi;
-      if (a.kx_out) {
-        a.kx_out[base + cell] = kx;
-        a.ky_out[base + cell] = ky;
+      wXd[t] = xd;
+      wXm[t] = xm;
+      // Psi on row r - P (meaningful once the window is full)
+      T* const gxr = s_gx[ring];
+      T* const gyr = s_gy[ring];
+      gxr[lane] = yrot(wXd, cm, t);
+      gyr[lane] = yrot(wXm, cd, t);
+      __syncthreads();
+      T mx = 0, my = 0;
+      if (lane >= P && lane < kStripW - P) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          mx += cm[u] * gxr[lane - P + u];
+          my += cm[u] * gyr[lane - P + u];
+        }
       }
-      if (a.kx_out_f) {
-        a.kx_out_f[base + cell] = float(kx);
-        a.ky_out_f[base + cell] = float(ky);
+      wMx[t] = mx;
+      wMy[t] = my;
+      const int o = r - 2 * P;
+      if (o >= y0 && writer) {
+        const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of Psi row o
+        const T px = s_gx[cs][lane], py = s_gy[cs][lane];
+        const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+        const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+        const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
+                          aksq * rx * rx * h / (eps + tabs(mu) * px * px));
+        const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
+                          aksq * ry * ry * h / (eps + tabs(nu) * py * py));
+        const size_t cell = size_t(o) * n + gi;
+        if (a.kx_out) {
+          a.kx_out[base + cell] = kx;
+          a.ky_out[base + cell] = ky;
+        }
+        if (a.kx_out_f) {
+          a.kx_out_f[base + cell] = float(kx);
+          a.ky_out_f[base + cell] = float(ky);
+        }
       }
+      ring = ring + 1 == D ? 0 : ring + 1;
     }
   }
 }
@@ -542,22 +582,39 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
-  T p0, p1 = 0;
-  auto load_row = [&](int r, T& vp0, T& vp1) {
-    const int cr = clampi(r, 0, n - 1);
-    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-    const size_t ro = size_t(cr) * n;
-    vp0 = (zy || zx0) ? T(0) : psi[ro + cc0];
-    if (lane < 2 * P) vp1 = (zy || zx1) ? T(0) : psi[ro + cc1];
+  // the psi row and the per-cell values of the output row it completes (emission, rhs, sigma_t)
+  // are loaded one step ahead
+  // loads are unconditional, from clamped addresses (halo rule and unused values applied at the
+  // use), so that no join waits for a load in flight
+  T p0, p1, fe0, fe1, fe2, frh, fs;
+  const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
+  const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
+  const T* __restrict__ E1g = p1mom ? Eg + ncell : Eg;
+  const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
+  const T* __restrict__ sigg = a.L.sigma_t + size_t(g) * ncell;
+  const T* __restrict__ rhsp = has_rhs ? a.rhs + base : Eg;
+  const int colc = clampi(col, 0, n - 1);
+  auto load_row = [&](int r) {
+    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    p0 = psi[ro + cc0];
+    p1 = psi[ro + cc1];
+    const size_t cell = size_t(clampi(r - 4 * P, 0, n - 1)) * n + colc;
+    fe0 = Eg[cell];
+    fe1 = E1g[cell];
+    fe2 = E2g[cell];
+    frh = rhsp[cell];
+    fs = sigg[cell];
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
-  load_row(rbeg, p0, p1);
+  load_row(rbeg);
   for (int r = rbeg; r < rend; ++r) {
     const int slot = ((r % PR) + PR) % PR;
     __syncthreads();                        // stage C of the previous step read the slot reused here
-    s_psi[slot][lane] = p0;
-    if (lane < 2 * P) s_psi[slot][kStripW + lane] = p1;
-    if (r + 1 < rend) load_row(r + 1, p0, p1);
+    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+    s_psi[slot][lane] = (zy || zx0) ? T(0) : p0;
+    if (lane < 2 * P) s_psi[slot][kStripW + lane] = (zy || zx1) ? T(0) : p1;
+    const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+    load_row(r + 1);   // past the last row this reloads a clamped row, unused
     __syncthreads();
     // A: Psi of row r - P
     {
@@ -647,11 +704,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       const T dx = ckx[0] * ypass(wA1x, cm) + ypass(wA2x, cm) - psc * ypass(wA3x, cm);
       const T dy = cky[0] * ypass(wA1y, ck) + ypass(wA2y, ck) - psc * ypass(wA3y, ck);
       const size_t cell = size_t(o) * n + col;
-      const size_t eb = size_t(g) * a.nmomE * ncell + cell;
-      T q = a.E[eb];
-      if (a.nmomE > 1) q += mu * a.E[eb + ncell] + nu * a.E[eb + 2 * ncell];
-      if (a.rhs) q += a.rhs[base + cell];
-      const T sig = a.L.sigma_t[size_t(g) * ncell + cell];
+      T q = e0;
+      if (p1mom) q += mu * e1 + nu * e2;
+      if (has_rhs) q += rh;
       const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
       if (a.mode == 0) {
         const T val = a.sign * rho;
@@ -713,6 +768,12 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
 }
 
 // correction sweep on one level: e_new = e + (rhs - A_up e - sigma_t e) / d
+// XMODE 0: e read from xin (same level); 1: e = UpSamp of the next coarser level's xin; 2: e = 0.
+// A block is 64 columns x (blockDim / 64) row groups; each thread owns one column of kCorrRows
+// rows and walks them in the ordinate's downwind y order, so the upwind y neighbour is the value
+// it read one row before (every e value is loaded once for the centre and once, from cache, as an
+// x neighbour).  With acc the new value is added to acc instead of being written to xout.
+constexpr int kCorrRows = 8;
 template <typename T, int XMODE>
 __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
                                                          const T* __restrict__ xin, int nac,
@@ -720,37 +781,56 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
                                                          T* __restrict__ xout, T* __restrict__ acc) {
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
-  const size_t ncell = size_t(n) * n;
-  const int cell = int(blockIdx.x) * int(blockDim.x) + int(threadIdx.x);
-  if (cell >= int(ncell)) return;
+  const int ntx = (n + 63) >> 6;
+  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
+  const int i = tx * 64 + int(threadIdx.x & 63);
+  const int jb = (ty * int(blockDim.x >> 6) + int(threadIdx.x >> 6)) * kCorrRows;
+  if (i >= n || jb >= n) return;
+  const int je = min(jb + kCorrRows, n);
   const int dir = blockIdx.y, g = blockIdx.z;
-  const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
-  const int j = cell / n, i = cell - j * n;
+  const size_t ncell = size_t(n) * n;
+  const size_t plane = (size_t(g) * nd + dir) * ncell;
   const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
   const int iu = mu > T(0) ? i - 1 : i + 1;
-  const int ju = nu > T(0) ? j - 1 : j + 1;
-  const bool xin_dom = iu >= 0 && iu < n, yin_dom = ju >= 0 && ju < n;
+  const bool xin_dom = iu >= 0 && iu < n;
   const bool xvac = mu > T(0) ? (bc_vac & 1) : (bc_vac & 2);
   const bool yvac = nu > T(0) ? (bc_vac & 4) : (bc_vac & 8);
-  T ec = 0, ex = 0, ey = 0;
-  if (XMODE == 0) {
-    ec = xin[idx];
-    ex = xin_dom ? xin[idx + (iu - i)] : (xvac ? T(0) : ec);
-    ey = yin_dom ? xin[idx + ptrdiff_t(ju - j) * n] : (yvac ? T(0) : ec);
-  } else if (XMODE == 1) {
-    const int nc = n >> 1;
-    const T* src = xin + (size_t(g) * (size_t(8) * (nac * nac)) + parent_dir_dev(dir, L.dims.na)) *
-                             (size_t(nc) * nc);
-    ec = src[size_t(j >> 1) * nc + (i >> 1)];
-    ex = xin_dom ? src[size_t(j >> 1) * nc + (iu >> 1)] : (xvac ? T(0) : ec);
-    ey = yin_dom ? src[size_t(ju >> 1) * nc + (i >> 1)] : (yvac ? T(0) : ec);
-  }
   const T amu = tabs(mu) / h, anu = tabs(nu) / h;
-  const T sig = L.sigma_t[size_t(g) * ncell + cell];
-  const T r = rhs[idx] - amu * (ec - ex) - anu * (ec - ey) - sig * ec;
-  const T enew = ec + r / (amu + anu + sig);
-  if (acc) acc[idx] += enew;
-  else xout[idx] = enew;
+  const T* __restrict__ sigma = L.sigma_t + size_t(g) * ncell;
+  // coarse source of XMODE 1: the parent ordinate's plane on the grid of half the size
+  const int nc = n >> 1;
+  const T* __restrict__ src = xin;
+  if (XMODE == 1)
+    src = xin + (size_t(g) * (size_t(8) * (nac * nac)) + parent_dir_dev(dir, L.dims.na)) * (size_t(nc) * nc);
+  auto value = [&](int jj, int ii) -> T {
+    if (XMODE == 0) return xin[plane + size_t(jj) * n + ii];
+    if (XMODE == 1) return src[size_t(jj >> 1) * nc + (ii >> 1)];
+    return T(0);
+  };
+  const bool down = nu > T(0);          // upwind row j - 1: walk with increasing j
+  const int j0 = down ? jb : je - 1;
+  const int ju0 = down ? j0 - 1 : j0 + 1;
+  bool prev_in = ju0 >= 0 && ju0 < n;
+  T eprev = (XMODE != 2 && prev_in) ? value(ju0, i) : T(0);
+#pragma unroll
+  for (int t = 0; t < kCorrRows; ++t) {
+    const int j = down ? j0 + t : j0 - t;
+    if (j < jb || j >= je) break;
+    const size_t cell = size_t(j) * n + i;
+    T ec = 0, ex = 0;
+    if (XMODE != 2) {
+      ec = value(j, i);
+      ex = xin_dom ? value(j, iu) : (xvac ? T(0) : ec);
+    }
+    const T ey = prev_in ? eprev : (yvac ? T(0) : ec);
+    const T sig = sigma[cell];
+    const T r = rhs[plane + cell] - amu * (ec - ex) - anu * (ec - ey) - sig * ec;
+    const T enew = ec + r / (amu + anu + sig);
+    if (acc) acc[plane + cell] += enew;
+    else xout[plane + cell] = enew;
+    eprev = ec;
+    prev_in = true;
+  }
 }
 
 // restriction: coarse = sum_{child ordinates, 2x2 cells} w_n rho h^2 / (w_N H^2)
@@ -942,8 +1022,7 @@ hipError_t launch_emission(const LevelDims& d, const T* phi, const T* ss, int nl
 }
 
 template <typename T>
-hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
-                     const PGLaunch<T>& o, hipStream_t s) {
+PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp, const PGLaunch<T>& o) {
   PGArgs<T> a{};
   a.L = L;
   a.st = st;
@@ -960,6 +1039,35 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.mode = o.mode;
   a.sign = o.sign;
   a.strip_h = o.strip_h;
+  return a;
+}
+
+template <typename T>
+hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
+                                 const PGLaunch<T>& o, hipStream_t s) {
+  if (!o.kx_out || !o.ky_out) return hipErrorInvalidValue;
+  PGArgs<T> a = pg_args(L, st, pp, o);
+  a.kx_out = o.kx_out;
+  a.ky_out = o.ky_out;
+  a.kx_out_f = o.kx_out_f;
+  a.ky_out_f = o.ky_out_f;
+  const int n = L.dims.n;
+  const int ow = kStripW - 2 * p;
+  a.ntx = (n + ow - 1) / ow;
+  const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
+  switch (p) {
+    case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_pg_diffusivity<3, T>), grid, dim3(kStripW), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
+                     const PGLaunch<T>& o, hipStream_t s) {
+  PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
     // fused: the diffusivities of psi are formed on the fly
@@ -979,23 +1087,9 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
     return hipGetLastError();
   }
   if (!o.kx_in) {
-    // diffusivities of psi first (into kx_out / ky_out, and / or their float copies)
-    if (!o.kx_out) return hipErrorInvalidValue;
-    a.kx_out = o.kx_out;
-    a.ky_out = o.ky_out;
-    a.kx_out_f = o.kx_out_f;
-    a.ky_out_f = o.ky_out_f;
-    const int ow = kStripW - 2 * p;
-    a.ntx = (n + ow - 1) / ow;
-    const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
-    switch (p) {
-      case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_pg_diffusivity<3, T>), grid, dim3(kStripW), 0, s, a); break;
-      default: return hipErrorInvalidValue;
-    }
-    a.kx_out = a.ky_out = nullptr;
-    a.kx_out_f = a.ky_out_f = nullptr;
+    // diffusivities of psi first (into kx_out / ky_out, and their float copies if asked)
+    const hipError_t e = launch_pg_diffusivity(p, L, st, pp, o, s);
+    if (e != hipSuccess) return e;
     a.kx_in = o.kx_out;
     a.ky_in = o.ky_out;
   } else {
@@ -1036,8 +1130,11 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
                                     int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
-  const size_t nc = size_t(L.dims.n) * L.dims.n;
-  const dim3 grid(unsigned((nc + block - 1) / block), L.dims.nd, L.dims.G), blk(block);
+  if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
+  const int n = L.dims.n;
+  const int rows_per_block = (block / 64) * kCorrRows;
+  const unsigned nb = unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block);
+  const dim3 grid(nb, L.dims.nd, L.dims.G), blk(block);
   if (xmode == 0)
     hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
   else if (xmode == 1)
@@ -1132,6 +1229,8 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
                                          hipStream_t);                                              \
   template hipError_t launch_pg<T>(int, const LevelData<T>&, const Stencils<T>&, const PGParams&,   \
                                    const PGLaunch<T>&, hipStream_t);                                \
+  template hipError_t launch_pg_diffusivity<T>(int, const LevelData<T>&, const Stencils<T>&,        \
+                                               const PGParams&, const PGLaunch<T>&, hipStream_t);   \
   template hipError_t launch_upwind_full<T>(const LevelData<T>&, int, const T*, const T*, int, T*,  \
                                             int, T, const T*, hipStream_t);                         \
   template hipError_t launch_upwind_correction<T>(const LevelData<T>&, int, const T*, int, int,     \
