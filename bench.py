@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--workload", default="c1_mixed")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-tolerance and batched measurements")
+    ap.add_argument("--launch-shape", default=None,
+                    help="strip_h,corr_block,pg_fused for the timed problem (default: the library's)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
                     help="before the workload, run an elementwise copy kernel (torch.neg) of this many "
                          "MiB three times, as the reference for hardware byte counters")
@@ -244,6 +246,8 @@ def main():
                              precision=ctf.FP32_IR, n_inner=2)
     prob = ctf.Problem(cfg, st, ss, src)
     del st, ss, src
+    if args.launch_shape:
+        prob.set_launch_shape(*[int(v) for v in args.launch_shape.split(",")])
     psi = prob.zeros()
     torch.cuda.synchronize()
     print(f"[bench] workload {w.name}: N={w.N} p={w.p} n_dir={w.n_dir} G={w.G} DOF={w.dof}",
@@ -299,7 +303,8 @@ def main():
         "config": {"workload": f"{w.name}: {w.N}x{w.N} nodes, p={w.p} ConvFEM + non-linear PG, "
                                f"{w.n_dir} ordinates, {w.G} groups downscatter; step = f64 residual"
                                f" + {cfg.n_inner} f32 sawtooth cycles + f64 update",
-                   "dof": w.dof, "cycles_per_step": cfg.n_inner, "outer_precision": "f64"},
+                   "dof": w.dof, "cycles_per_step": cfg.n_inner, "outer_precision": "f64",
+                   "launch_shape": dict(zip(("strip_h", "corr_block", "pg_fused"), prob.launch_shape()))},
         "roofline": roof,
         "kernels": kernels,
     }

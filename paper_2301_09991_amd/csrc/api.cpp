@@ -129,9 +129,9 @@ struct ctf_problem {
   PGParams pp{};
   int bc_vac = 0;
   int* active = nullptr;     // device flag read by every kernel (0: converged member of a batch)
-  int strip_h = 64;          // tuned launch shapes
+  int strip_h = 128;         // launch shapes (defaults: fastest measured on the 256^2 p = 2 workload)
   int corr_block = 256;
-  int pg_fused = 0;          // non-linear PG: diffusivities formed in the same pass (1) or stored (0)
+  int pg_fused = 1;          // non-linear PG: diffusivities formed in the same pass (1) or stored (0)
   // learned coarse-grid correction
   int cnn_level = -1;
   bool cnn_on = false;
@@ -1274,7 +1274,7 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
     int best_f = P->pg_fused;
     if (c.discretisation != CTF_UPWIND) {
       for (int fz = 0; fz < (c.discretisation == CTF_CONVFEM_PG ? 2 : 1); ++fz)
-      for (int h : {8, 16, 32, 64, 128}) {
+      for (int h : {8, 16, 32, 64, 128, 256}) {
         P->strip_h = h;
         P->pg_fused = fz;
         double ms = 0.0;

@@ -15,11 +15,35 @@ __device__ __forceinline__ bool idle(const int* active) { return active && *acti
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-template <typename T>
-__device__ __forceinline__ T tabs(T x) { return x < T(0) ? -x : x; }
+// |x| as a source modifier and min as one instruction (the operands here are never NaN)
+__device__ __forceinline__ float tabs(float x) { return __builtin_fabsf(x); }
+__device__ __forceinline__ double tabs(double x) { return __builtin_fabs(x); }
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
 
+// a / b for b > 0: float32 as a times the hardware reciprocal (within 2 ulp; the float32 kernels
+// serve the refinement's inner cycles), float64 exactly rounded.
+__device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+
+// Element at a 32-bit byte offset from a wave-uniform row pointer, so that the access is a scalar
+// base plus a 32-bit vector offset (no 64-bit vector address arithmetic per access).
 template <typename T>
-__device__ __forceinline__ T tmin(T a, T b) { return b < a ? b : a; }
+__device__ __forceinline__ const T& at(const T* row, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(row) + boff);
+}
+template <typename T>
+__device__ __forceinline__ T& at(T* row, unsigned boff) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + boff);
+}
+
+// Anisotropic diffusivity of one direction component (eq. ano-k):
+//   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
+template <typename T>
+__device__ __forceinline__ T pg_k(T mu, T R, T Psi, T h, T akabs, T aksq, T eps) {
+  return tmin(tmin(h * tabs(mu), qdiv(akabs * tabs(R) * h, eps + tabs(Psi))),
+              qdiv(aksq * R * R * h, eps + tabs(mu) * Psi * Psi));
+}
 
 __device__ __forceinline__ int parent_dir_dev(int n, int na) {
   if (na == 1) return n;
@@ -274,9 +298,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int D = P + 2;   // LDS ring of input rows: the current row and the P rows above it
-  __shared__ T s_psi[D][RW];
-  __shared__ T s_kx[D][RW];
-  __shared__ T s_ky[D][RW];
+  __shared__ T s_row[D][3][RW];   // psi, k_x, k_y side by side (one base address per row)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
@@ -317,21 +339,23 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
   const T* __restrict__ sigg = a.L.sigma_t + size_t(g) * ncell;
   const T* __restrict__ rhsp = has_rhs ? a.rhs + base : Eg;
-  const int gic = min(gi, n - 1);
+  const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
+  const unsigned bc = unsigned(min(gi, n - 1)) * sizeof(T);
+  const unsigned bo = unsigned(gi) * sizeof(T), bof = unsigned(gi) * sizeof(float);
   auto load_row = [&](int r) {
     const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
-    p0 = psi[ro + cc0];
-    k0 = kxin[ro + cc0];
-    q0 = kyin[ro + cc0];
-    p1 = psi[ro + cc1];
-    k1 = kxin[ro + cc1];
-    q1 = kyin[ro + cc1];
-    const size_t cell = size_t(clampi(r - P, 0, n - 1)) * n + gic;
-    fe0 = Eg[cell];
-    fe1 = E1g[cell];
-    fe2 = E2g[cell];
-    frh = rhsp[cell];
-    fs = sigg[cell];
+    p0 = at(psi + ro, b0);
+    k0 = at(kxin + ro, b0);
+    q0 = at(kyin + ro, b0);
+    p1 = at(psi + ro, b1);
+    k1 = at(kxin + ro, b1);
+    q1 = at(kyin + ro, b1);
+    const size_t co = size_t(clampi(r - P, 0, n - 1)) * n;
+    fe0 = at(Eg + co, bc);
+    fe1 = at(E1g + co, bc);
+    fe2 = at(E2g + co, bc);
+    frh = at(rhsp + co, bc);
+    fs = at(sigg + co, bc);
   };
   const int rbeg = y0 - P, rend = yend + P;
   load_row(rbeg);
@@ -341,9 +365,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
     for (int t = 0; t < W; ++t) {
       const int r = r0 + t;
       if (r >= rend) break;
-      T* const rp = s_psi[ring];
-      T* const rk = s_kx[ring];
-      T* const rq = s_ky[ring];
+      T* const rp = s_row[ring][0];
+      T* const rk = s_row[ring][1];
+      T* const rq = s_row[ring][2];
       const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
       rp[lane] = (zy || zx0) ? T(0) : p0;
       rk[lane] = k0;
@@ -378,22 +402,22 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
       const int o = r - P;
       if (o >= y0 && gi < n) {
         const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of row o
-        const T pc = s_psi[cs][lane + P], kxc = s_kx[cs][lane + P], kyc = s_ky[cs][lane + P];
+        const T pc = s_row[cs][0][lane + P], kxc = s_row[cs][1][lane + P], kyc = s_row[cs][2][lane + P];
         const T px = yrot(wXd, cm, t), py = yrot(wXm, cd, t);
         const T dx = kxc * yrot(wXk, cm, t) + yrot(wA2x, cm, t) - pc * yrot(wA3x, cm, t);
         const T dy = kyc * yrot(wXm, ck, t) + yrot(wA2y, ck, t) - pc * yrot(wA3y, ck, t);
-        const size_t cell = size_t(o) * n + gi;
+        const size_t ro = base + size_t(o) * n;
         T q = e0;
         if (p1mom) q += mu * e1 + nu * e2;
         if (has_rhs) q += rh;
         const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
         if (a.mode == 0) {
           const T val = a.sign * rho;
-          if (a.out) a.out[base + cell] = val;
-          if (a.out_f) a.out_f[base + cell] = float(val);
+          if (a.out) at(a.out + ro, bo) = val;
+          if (a.out_f) at(a.out_f + ro, bof) = float(val);
           acc += double(val) * double(val);
         } else {
-          a.out[base + cell] = pc + rho / (diag + a.beta * sig);
+          at(a.out + ro, bo) = pc + qdiv(rho, diag + a.beta * sig);
         }
       }
       ring = ring + 1 == D ? 0 : ring + 1;
@@ -427,8 +451,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
   constexpr int D = P + 2;              // LDS ring of Psi rows: the newest and the P rows above it
   __shared__ T s_psi[RW];
-  __shared__ T s_gx[D][kStripW];
-  __shared__ T s_gy[D][kStripW];
+  __shared__ T s_g[D][2][kStripW];   // Psi_x, Psi_y side by side
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
@@ -458,10 +481,12 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   // rows are loaded one ahead, unconditionally from clamped addresses (the halo rule is applied
   // when the row is written to LDS), so that no join waits for a load in flight
   T p0, p1;
+  const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
+  const unsigned bo = unsigned(gi) * sizeof(T), bof = unsigned(gi) * sizeof(float);
   auto load_row = [&](int r) {
     const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
-    p0 = psi[ro + cc0];
-    p1 = psi[ro + cc1];
+    p0 = at(psi + ro, b0);
+    p1 = at(psi + ro, b1);
   };
   const int rbeg = y0 - 2 * P, rend = yend + 2 * P;
   load_row(rbeg);
@@ -486,8 +511,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       wXd[t] = xd;
       wXm[t] = xm;
       // Psi on row r - P (meaningful once the window is full)
-      T* const gxr = s_gx[ring];
-      T* const gyr = s_gy[ring];
+      T* const gxr = s_g[ring][0];
+      T* const gyr = s_g[ring][1];
       gxr[lane] = yrot(wXd, cm, t);
       gyr[lane] = yrot(wXm, cd, t);
       __syncthreads();
@@ -504,21 +529,19 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       const int o = r - 2 * P;
       if (o >= y0 && writer) {
         const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of Psi row o
-        const T px = s_gx[cs][lane], py = s_gy[cs][lane];
+        const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
         const T rx = ar * mu * (yrot(wMx, cm, t) - px);
         const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-        const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
-                          aksq * rx * rx * h / (eps + tabs(mu) * px * px));
-        const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
-                          aksq * ry * ry * h / (eps + tabs(nu) * py * py));
-        const size_t cell = size_t(o) * n + gi;
+        const T kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
+        const T ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+        const size_t ro = base + size_t(o) * n;
         if (a.kx_out) {
-          a.kx_out[base + cell] = kx;
-          a.ky_out[base + cell] = ky;
+          at(a.kx_out + ro, bo) = kx;
+          at(a.ky_out + ro, bo) = ky;
         }
         if (a.kx_out_f) {
-          a.kx_out_f[base + cell] = float(kx);
-          a.ky_out_f[base + cell] = float(ky);
+          at(a.kx_out_f + ro, bof) = float(kx);
+          at(a.ky_out_f + ro, bof) = float(ky);
         }
       }
       ring = ring + 1 == D ? 0 : ring + 1;
@@ -531,22 +554,30 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
 // xs .. xs + 63 - 4P; rows stream through a four-stage pipeline (row r loaded at step r):
 //   A  Psi_x, Psi_y of row r - P          (x-pass on the psi row, y-pass over registers)
 //   B  R_x, R_y and k_x, k_y of row r - 2P (x-pass on the Psi row, y-pass over registers)
-//   C  x-passes of psi, k psi, k for row s = r - 3P (psi and k rows from LDS rings; the k
-//      halo copies the nearest interior row / column)
+//   C  x-passes of psi, k psi, k for row r - 3P (the k halo copies the nearest interior row and
+//      column)
 //   D  output row r - 4P (y-passes over registers)
+// psi, Psi and k rows live in LDS rings deep enough for every later stage that reads them (the
+// centre values of row r - 4P included); the y-pass windows rotate with the unrolled step.
+template <int P>
+__device__ __forceinline__ int ring_slot(int row, int depth) {
+  const int m = row % depth;
+  return m < 0 ? m + depth : m;
+}
+
 template <int P, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
   constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
-  constexpr int PR = 3 * P + 1;         // psi rows kept (rows r - 3P .. r)
-  constexpr int KR = P + 1;             // k rows kept
+  constexpr int PR = 4 * P + 1;         // psi rows kept (r - 4P .. r)
+  constexpr int GR = 3 * P + 1;         // Psi rows kept (r - 4P .. r - P)
+  constexpr int KR = 2 * P + 1;         // k rows kept (r - 4P .. r - 2P)
   constexpr int OW = kStripW - 4 * P;   // columns written per strip
+  // x and y components side by side, so that both are addressed from one base
   __shared__ T s_psi[PR][RW];
-  __shared__ T s_gx[kStripW];
-  __shared__ T s_gy[kStripW];
-  __shared__ T s_kx[KR][kStripW];
-  __shared__ T s_ky[KR][kStripW];
+  __shared__ T s_g[GR][2][kStripW];   // Psi_x, Psi_y
+  __shared__ T s_k[KR][2][kStripW];   // k_x, k_y (columns outside the domain: the k halo copy)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
@@ -565,10 +596,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     ck[t] = a.st.k[t];
   }
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
-  T cgx[P + 1] = {}, cgy[P + 1] = {};
-  T ogx[3 * P + 1] = {}, ogy[3 * P + 1] = {};
   T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
-  T cpsi[P + 1] = {}, ckx[P + 1] = {}, cky[P + 1] = {};
   // psi row loads: lane l -> column c0 - P + l; lanes < 2P also column c0 - P + 64 + l
   const int lc0 = c0 - P + lane, lc1 = lc0 + kStripW;
   const int cc0 = clampi(lc0, 0, n - 1), cc1 = clampi(lc1, 0, n - 1);
@@ -577,13 +605,15 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const int col = c0 + lane;
   const bool writer = lane >= 2 * P && lane < kStripW - 2 * P && col < n;
   const bool kvalid = lane >= P && lane < kStripW - P;
-  // lane holding the k of the clamped column of lane + u - P (for the k halo copy)
+  const bool cvalid = lane >= P && lane < kStripW - P;
+  // strips that reach past the domain copy k of the nearest interior column into those columns
+  const bool edge_strip = c0 < 0 || c0 + kStripW > n;
+  const bool outside = col < 0 || col >= n;
+  const int kcl = clampi(col, 0, n - 1) - c0;   // lane of the nearest interior column
   const int yend = min(y0 + a.strip_h, n);
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
-  // the psi row and the per-cell values of the output row it completes (emission, rhs, sigma_t)
-  // are loaded one step ahead
   // loads are unconditional, from clamped addresses (halo rule and unused values applied at the
   // use), so that no join waits for a load in flight
   T p0, p1, fe0, fe1, fe2, frh, fs;
@@ -593,129 +623,140 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
   const T* __restrict__ sigg = a.L.sigma_t + size_t(g) * ncell;
   const T* __restrict__ rhsp = has_rhs ? a.rhs + base : Eg;
-  const int colc = clampi(col, 0, n - 1);
+  const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
+  const unsigned bc = unsigned(clampi(col, 0, n - 1)) * sizeof(T);
+  const unsigned bo = unsigned(col) * sizeof(T), bof = unsigned(col) * sizeof(float);
   auto load_row = [&](int r) {
     const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
-    p0 = psi[ro + cc0];
-    p1 = psi[ro + cc1];
-    const size_t cell = size_t(clampi(r - 4 * P, 0, n - 1)) * n + colc;
-    fe0 = Eg[cell];
-    fe1 = E1g[cell];
-    fe2 = E2g[cell];
-    frh = rhsp[cell];
-    fs = sigg[cell];
+    p0 = at(psi + ro, b0);
+    p1 = at(psi + ro, b1);
+    const size_t co = size_t(clampi(r - 4 * P, 0, n - 1)) * n;
+    fe0 = at(Eg + co, bc);
+    fe1 = at(E1g + co, bc);
+    fe2 = at(E2g + co, bc);
+    frh = at(rhsp + co, bc);
+    fs = at(sigg + co, bc);
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg);
-  for (int r = rbeg; r < rend; ++r) {
-    const int slot = ((r % PR) + PR) % PR;
-    __syncthreads();                        // stage C of the previous step read the slot reused here
-    const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-    s_psi[slot][lane] = (zy || zx0) ? T(0) : p0;
-    if (lane < 2 * P) s_psi[slot][kStripW + lane] = (zy || zx1) ? T(0) : p1;
-    const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
-    load_row(r + 1);   // past the last row this reloads a clamped row, unused
-    __syncthreads();
-    // A: Psi of row r - P
-    {
-      T xd = 0, xm = 0;
+  for (int r0 = rbeg; r0 < rend; r0 += W) {
 #pragma unroll
-      for (int u = 0; u < W; ++u) {
-        const T v = s_psi[slot][lane + u];
-        xd += cd[u] * v;
-        xm += cm[u] * v;
-      }
-      push(wXd, xd);
-      push(wXm, xm);
-      const T gx = ypass(wXd, cm), gy = ypass(wXm, cd);
-      s_gx[lane] = gx;
-      s_gy[lane] = gy;
-      push(cgx, gx);
-      push(cgy, gy);
-      push(ogx, gx);
-      push(ogy, gy);
-    }
-    __syncthreads();
-    // B: k of row r - 2P
-    {
-      T mx = 0, my = 0;
-      if (kvalid) {
+    for (int t = 0; t < W; ++t) {
+      const int r = r0 + t;
+      if (r >= rend) break;
+      T* const prow = s_psi[ring_slot<P>(r, PR)];
+      const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
+      prow[lane] = (zy || zx0) ? T(0) : p0;
+      if (lane < 2 * P) prow[kStripW + lane] = (zy || zx1) ? T(0) : p1;
+      const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+      load_row(r + 1);   // past the last row this reloads a clamped row, unused
+      __syncthreads();
+      // A: Psi of row r - P
+      T* const gxr = s_g[ring_slot<P>(r - P, GR)][0];
+      T* const gyr = s_g[ring_slot<P>(r - P, GR)][1];
+      {
+        T xd = 0, xm = 0;
 #pragma unroll
         for (int u = 0; u < W; ++u) {
-          mx += cm[u] * s_gx[lane - P + u];
-          my += cm[u] * s_gy[lane - P + u];
+          const T v = prow[lane + u];
+          xd += cd[u] * v;
+          xm += cm[u] * v;
         }
+        wXd[t] = xd;
+        wXm[t] = xm;
+        gxr[lane] = yrot(wXd, cm, t);
+        gyr[lane] = yrot(wXm, cd, t);
       }
-      push(wMx, mx);
-      push(wMy, my);
-      const int rk = r - 2 * P;
-      if (rk >= 0 && rk < n) {
-        const T px = cgx[0], py = cgy[0];
-        const T rx = ar * mu * (ypass(wMx, cm) - px);
-        const T ry = ar * nu * (ypass(wMy, cm) - py);
-        const T kx = tmin(tmin(h * tabs(mu), akabs * tabs(rx) * h / (eps + tabs(px))),
-                          aksq * rx * rx * h / (eps + tabs(mu) * px * px));
-        const T ky = tmin(tmin(h * tabs(nu), akabs * tabs(ry) * h / (eps + tabs(py))),
-                          aksq * ry * ry * h / (eps + tabs(nu) * py * py));
-        s_kx[rk % KR][lane] = kx;
-        s_ky[rk % KR][lane] = ky;
-      }
-    }
-    __syncthreads();
-    // C: x-passes of row s = r - 3P (k of the clamped row and columns)
-    {
-      const int srow = r - 3 * P;
-      const int sslot = ((srow % PR) + PR) % PR;
-      const int kslot = clampi(srow, 0, n - 1) % KR;
-      T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0, pc = 0, kxc = 0, kyc = 0;
-      if (lane >= P && lane < kStripW - P) {
+      __syncthreads();
+      // B: k of row r - 2P
+      {
+        T mx = 0, my = 0;
+        if (kvalid) {
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-          const int kl = clampi(col + u - P, 0, n - 1) - c0;   // lane of the clamped column
-          const T v = s_psi[sslot][lane + u];
-          const T kv = s_kx[kslot][kl], qv = s_ky[kslot][kl];
-          a1x += ck[u] * v;
-          a2x += ck[u] * (kv * v);
-          a3x += ck[u] * kv;
-          a1y += cm[u] * v;
-          a2y += cm[u] * (qv * v);
-          a3y += cm[u] * qv;
+          for (int u = 0; u < W; ++u) {
+            mx += cm[u] * gxr[lane - P + u];
+            my += cm[u] * gyr[lane - P + u];
+          }
         }
-        pc = s_psi[sslot][lane + P];
-        const int kc = clampi(col, 0, n - 1) - c0;
-        kxc = s_kx[kslot][kc];
-        kyc = s_ky[kslot][kc];
+        wMx[t] = mx;
+        wMy[t] = my;
+        const int rk = r - 2 * P;
+        if (rk >= 0 && rk < n) {
+          const int gs = ring_slot<P>(rk, GR);
+          const T px = s_g[gs][0][lane], py = s_g[gs][1][lane];
+          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+          T(&kr)[2][kStripW] = s_k[ring_slot<P>(rk, KR)];
+          kr[0][lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
+          kr[1][lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          if (edge_strip) {
+            __syncthreads();
+            T ox = 0, oy = 0;
+            if (outside) {
+              ox = kr[0][kcl];
+              oy = kr[1][kcl];
+            }
+            __syncthreads();
+            if (outside) {
+              kr[0][lane] = ox;
+              kr[1][lane] = oy;
+            }
+          }
+        }
       }
-      push(wA1x, a1x);
-      push(wA2x, a2x);
-      push(wA3x, a3x);
-      push(wA1y, a1y);
-      push(wA2y, a2y);
-      push(wA3y, a3y);
-      push(cpsi, pc);
-      push(ckx, kxc);
-      push(cky, kyc);
-    }
-    // D: output row r - 4P
-    const int o = r - 4 * P;
-    if (o >= y0 && writer) {
-      const T px = ogx[0], py = ogy[0];
-      const T psc = cpsi[0];
-      const T dx = ckx[0] * ypass(wA1x, cm) + ypass(wA2x, cm) - psc * ypass(wA3x, cm);
-      const T dy = cky[0] * ypass(wA1y, ck) + ypass(wA2y, ck) - psc * ypass(wA3y, ck);
-      const size_t cell = size_t(o) * n + col;
-      T q = e0;
-      if (p1mom) q += mu * e1 + nu * e2;
-      if (has_rhs) q += rh;
-      const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
-      if (a.mode == 0) {
-        const T val = a.sign * rho;
-        if (a.out) a.out[base + cell] = val;
-        if (a.out_f) a.out_f[base + cell] = float(val);
-        acc += double(val) * double(val);
-      } else {
-        a.out[base + cell] = psc + rho / (diag + a.beta * sig);
+      __syncthreads();
+      // C: x-passes of row s = r - 3P (k of the clamped row and columns)
+      {
+        const int srow = r - 3 * P;
+        const T* const sp = s_psi[ring_slot<P>(srow, PR)];
+        const int ks = ring_slot<P>(clampi(srow, 0, n - 1), KR);
+        const T* const kxr = s_k[ks][0];
+        const T* const kyr = s_k[ks][1];
+        T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0;
+        if (cvalid) {
+#pragma unroll
+          for (int u = 0; u < W; ++u) {
+            const T v = sp[lane + u];
+            const T kv = kxr[lane - P + u], qv = kyr[lane - P + u];
+            a1x += ck[u] * v;
+            a2x += ck[u] * (kv * v);
+            a3x += ck[u] * kv;
+            a1y += cm[u] * v;
+            a2y += cm[u] * (qv * v);
+            a3y += cm[u] * qv;
+          }
+        }
+        wA1x[t] = a1x;
+        wA2x[t] = a2x;
+        wA3x[t] = a3x;
+        wA1y[t] = a1y;
+        wA2y[t] = a2y;
+        wA3y[t] = a3y;
       }
+      // D: output row r - 4P
+      const int o = r - 4 * P;
+      if (o >= y0 && writer) {
+        const int gs = ring_slot<P>(o, GR), ks = ring_slot<P>(o, KR);
+        const T px = s_g[gs][0][lane], py = s_g[gs][1][lane];
+        const T psc = s_psi[ring_slot<P>(o, PR)][lane + P];
+        const T kxc = s_k[ks][0][lane], kyc = s_k[ks][1][lane];
+        const T dx = kxc * yrot(wA1x, cm, t) + yrot(wA2x, cm, t) - psc * yrot(wA3x, cm, t);
+        const T dy = kyc * yrot(wA1y, ck, t) + yrot(wA2y, ck, t) - psc * yrot(wA3y, ck, t);
+        const size_t ro = base + size_t(o) * n;
+        T q = e0;
+        if (p1mom) q += mu * e1 + nu * e2;
+        if (has_rhs) q += rh;
+        const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
+        if (a.mode == 0) {
+          const T val = a.sign * rho;
+          if (a.out) at(a.out + ro, bo) = val;
+          if (a.out_f) at(a.out_f + ro, bof) = float(val);
+          acc += double(val) * double(val);
+        } else {
+          at(a.out + ro, bo) = psc + qdiv(rho, diag + a.beta * sig);
+        }
+      }
+      __syncthreads();   // the next step overwrites ring slots read above
     }
   }
   if (a.partial) {
