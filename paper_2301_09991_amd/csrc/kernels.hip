@@ -263,6 +263,23 @@ struct PGArgs {
 // registers, so every input value is read from HBM about once.
 constexpr int kStripW = 64;
 
+// Logical block of a strip kernel (grid: strips x ordinates x groups).  The hardware hands out
+// workgroups round-robin over the 8 XCDs by linear block id; the blocks one XCD receives get a
+// contiguous range of logical ids, so that each XCD streams whole (ordinate, group) planes strip
+// after strip and its own L2 keeps the per-cell data and the rows shared by neighbouring strips.
+constexpr unsigned kXcds = 8;
+struct StripBlock {
+  int strip, dir, g;
+};
+__device__ __forceinline__ StripBlock strip_block() {
+  const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
+  const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, rm = nb % kXcds;
+  const unsigned L = x * q + (x < rm ? x : rm) + k;
+  const unsigned pl = L / gridDim.x;
+  return StripBlock{int(L % gridDim.x), int(pl % gridDim.y), int(pl / gridDim.y)};
+}
+
 template <typename T, int W>
 __device__ __forceinline__ void push(T (&w)[W], T v) {
 #pragma unroll
@@ -301,8 +318,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   __shared__ T s_row[D][3][RW];   // psi, k_x, k_y side by side (one base address per row)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const int x0 = (blockIdx.x % a.ntx) * kStripW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
-  const int dir = blockIdx.y, g = blockIdx.z;
+  const StripBlock sb = strip_block();
+  const int x0 = (sb.strip % a.ntx) * kStripW, y0 = (sb.strip / a.ntx) * a.strip_h;
+  const int dir = sb.dir, g = sb.g;
   const size_t ncell = size_t(n) * n;
   const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
   const T mu = a.L.mu[dir], nu = a.L.nu[dir];
@@ -350,7 +368,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
     p1 = at(psi + ro, b1);
     k1 = at(kxin + ro, b1);
     q1 = at(kyin + ro, b1);
-    const size_t co = size_t(clampi(r - P, 0, n - 1)) * n;
+    const size_t co = size_t(clampi(r - P, y0, yend - 1)) * n;   // rows of this strip only
     fe0 = at(Eg + co, bc);
     fe1 = at(E1g + co, bc);
     fe2 = at(E2g + co, bc);
@@ -454,9 +472,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   __shared__ T s_g[D][2][kStripW];   // Psi_x, Psi_y side by side
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
+  const StripBlock sb = strip_block();
+  const int xs = (sb.strip % a.ntx) * OW, y0 = (sb.strip / a.ntx) * a.strip_h;
   const int x0 = xs - P;                 // column of lane 0 (Psi is formed for x0 .. x0 + 63)
-  const int dir = blockIdx.y, g = blockIdx.z;
+  const int dir = sb.dir, g = sb.g;
   const size_t ncell = size_t(n) * n;
   const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
   const T mu = a.L.mu[dir], nu = a.L.nu[dir];
@@ -580,9 +599,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   __shared__ T s_k[KR][2][kStripW];   // k_x, k_y (columns outside the domain: the k halo copy)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const int xs = (blockIdx.x % a.ntx) * OW, y0 = (blockIdx.x / a.ntx) * a.strip_h;
+  const StripBlock sb = strip_block();
+  const int xs = (sb.strip % a.ntx) * OW, y0 = (sb.strip / a.ntx) * a.strip_h;
   const int c0 = xs - 2 * P;            // column of lane 0
-  const int dir = blockIdx.y, g = blockIdx.z;
+  const int dir = sb.dir, g = sb.g;
   const size_t ncell = size_t(n) * n;
   const size_t base = (size_t(g) * a.L.dims.nd + dir) * ncell;
   const T mu = a.L.mu[dir], nu = a.L.nu[dir];
@@ -630,7 +650,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
     p0 = at(psi + ro, b0);
     p1 = at(psi + ro, b1);
-    const size_t co = size_t(clampi(r - 4 * P, 0, n - 1)) * n;
+    const size_t co = size_t(clampi(r - 4 * P, y0, yend - 1)) * n;   // rows of this strip only
     fe0 = at(Eg + co, bc);
     fe1 = at(E1g + co, bc);
     fe2 = at(E2g + co, bc);
