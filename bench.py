@@ -128,8 +128,9 @@ def time_to_tolerance(log):
     """Learned-correction workload (1024 x 1024 nodes, L = 32, p = 2, 512 ordinates, one group,
     c in [0.8, 0.99]), upwind discretisation: wall time of ctf_solve from psi = 0 to a float64
     relative residual of 1e-6 for plain float64 multigrid, float32 cycles + float64 refinement,
-    and the same with the learned coarse-grid correction (trained here, seeded, on 32^2 .. 128^2
-    problems of the same physical cell size at the correction level)."""
+    and the same with the learned coarse-grid correction, trained here on residual/error pairs
+    from 200 seeded solves at 128 x 128 (same L, so the correction level's 32 x 32 grid has the
+    same cell size H = 1 as the evaluation problem's)."""
     import torch
     from paper_2301_09991_amd import ctf, learned
     from workloads import WORKLOADS, Workload, make_inputs
@@ -138,9 +139,9 @@ def time_to_tolerance(log):
 
     def tw(N, seed, patch):
         return Workload(f"train{seed}", N, w.L, w.p, 2, 1, patch, "iso", "box_quarter_phys", w.c_range, seed)
-    train = ([(tw(32, 4000 + k, 1), 0) for k in range(40)] + [(tw(64, 4100 + k, 2), 1) for k in range(20)]
-             + [(tw(128, 4200 + k, 4), 2) for k in range(10)])
+    train = [(tw(128, 4000 + k, 4), 2) for k in range(200)]
     F, T = learned.generate_samples(train, make_inputs)
+    log(f"training samples from {len(train)} solves at 128x128 in {time.perf_counter() - t0:.1f} s")
     theta, hist = learned.train(F, T, epochs=150, batch=16, lr=2e-3, seed=0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0

@@ -119,7 +119,6 @@ struct ctf_problem {
   float* e_f = nullptr;    // float32 correction of a refinement step
   float* e_tmp_f = nullptr;
   float* r_f = nullptr;    // float32 right-hand side of the correction equation
-  float* psi32_f = nullptr;  // psi64 rounded (full-approximation refinement)
   double* partial = nullptr;
   double* scal = nullptr;  // device scalars
   int npartial = 0;
@@ -231,7 +230,6 @@ size_t layout(ctf_problem* P, char* base) {
     P->e_f = c.take<float>(P->dof(0));
     P->e_tmp_f = c.take<float>(P->dof(0));
     P->r_f = c.take<float>(P->dof(0));
-    P->psi32_f = cfg.discretisation == CTF_CONVFEM_PG ? c.take<float>(P->dof(0)) : nullptr;
   }
   if (cfg.cnn_level >= 0 && cfg.cnn_level < P->L) {
     const int nc = P->dims[cfg.cnn_level].n;
@@ -583,9 +581,8 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
   if (fas) {
     // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64)
-    CTF_HIP(launch_convert_d2f(psi, P->psi32_f, n, P->stream, P->active));
-    CTF_HIP(launch_copy<float>(P->e_f, P->psi32_f, n, P->stream, P->active));
-    int rc = inner_finest32(P, P->psi32_f, P->r_f, 0, -1.0f);
+    CTF_HIP(launch_convert_d2f(psi, P->e_f, n, P->stream, P->active));
+    int rc = inner_finest32(P, P->e_f, P->r_f, 0, -1.0f);
     if (rc) return rc;
   }
   int it = 0;
@@ -595,7 +592,7 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
     if (rc) return rc;
   }
   if (it > 0) {
-    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, P->psi32_f, n, P->stream, P->active));
+    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, n, P->stream, P->active));   // psi += u - fl32(psi)
     else CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream, P->active));
   }
   if (done) *done = it;

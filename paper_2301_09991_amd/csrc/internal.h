@@ -171,8 +171,8 @@ hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s);
 // y(double) += x(float)
 hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, const int* active = nullptr);
-// y(double) += u(float) - v(float)
-hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s,
+// y(double) += u(float) - fl32(y): the full-approximation update
+hipError_t launch_add_diff_f2d(double* y, const float* u, size_t n, hipStream_t s,
                                const int* active = nullptr);
 
 // ---- learned coarse-grid correction (cnn.hip) ---------------------------------------------------

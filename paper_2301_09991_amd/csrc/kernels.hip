@@ -1022,12 +1022,15 @@ __global__ __launch_bounds__(kBlock) void k_add_f2d(double* __restrict__ y, cons
   if (i < n) y[i] += double(x[i]);
 }
 
+// y += u - fl32(y): the full-approximation update, with the float32 start value re-derived from y
 __global__ __launch_bounds__(kBlock) void k_add_diff_f2d(double* __restrict__ y, const float* __restrict__ u,
-                                                          const float* __restrict__ v, size_t n,
-                                                          const int* active) {
+                                                          size_t n, const int* active) {
   if (idle(active)) return;
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  if (i < n) y[i] += double(u[i]) - double(v[i]);
+  if (i < n) {
+    const double yi = y[i];
+    y[i] = yi + (double(u[i]) - double(float(yi)));
+  }
 }
 
 __global__ void k_update_active(const double* __restrict__ norm2, double bnorm, double rtol,
@@ -1274,9 +1277,9 @@ hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_
   hipLaunchKernelGGL(k_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n);
   return hipGetLastError();
 }
-hipError_t launch_add_diff_f2d(double* y, const float* u, const float* v, size_t n, hipStream_t s,
+hipError_t launch_add_diff_f2d(double* y, const float* u, size_t n, hipStream_t s,
                                const int* active) {
-  hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, v, n, active);
+  hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, n, active);
   return hipGetLastError();
 }
 hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, const int* active) {
