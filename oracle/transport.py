@@ -81,9 +81,15 @@ def moments(psi, quad):
 
 def emission(psi, quad, sigma_s, source):
     """q[g, n, j, i] = [S_g + sum_g' s0(g'->g) Phi0_g' + 3 sum_g' s1(g'->g)(mu_n Phi1 + nu_n Phi2)]/4pi."""
-    G, nd = psi.shape[:2]
-    Phi = moments(psi, quad)
-    q = np.zeros(psi.shape)
+    return emission_from_moments(moments(psi, quad), quad, sigma_s, source)
+
+
+def emission_from_moments(Phi, quad, sigma_s, source):
+    """The emission above from given moments Phi[g, m, j, i], for the ordinates of ``quad`` (which
+    may be a subset of the set the moments were summed over)."""
+    G = Phi.shape[0]
+    nd = len(quad["mu"])
+    q = np.zeros((G, nd) + Phi.shape[2:])
     for g in range(G):
         iso = source[g].copy()
         for gp in range(G):

@@ -1,11 +1,13 @@
-"""Full-size checks on the benchmark's workload (256 x 256 nodes, p = 2, 512 ordinates, two groups
-with downscatter) in the launch configuration the benchmark times: the float64 residual on sampled
-ordinates of a random flux against the oracle, and properties of the refinement step at any size."""
+"""Full-size checks in the launch configuration the benchmark times (the library defaults): the
+float64 residual on sampled ordinates against the oracle for the benchmark's workload (256 x 256
+nodes, p = 2, 512 ordinates, two groups with downscatter), the largest workload (512 x 512, p = 3,
+2048 ordinates, 4 groups, P1: 2^31 DOF) and the learned-correction workload (1024 x 1024, 512
+ordinates), and properties of the refinement step at any size."""
 import numpy as np
 import pytest
 
 from oracle import multigrid as omg
-from oracle.transport import emission, pg_residual
+from oracle.transport import VACUUM, emission, pg_residual
 from workloads import WORKLOADS, make_inputs, random_field
 
 pytestmark = pytest.mark.gpu
@@ -54,3 +56,91 @@ def test_fullsize_refinement_steps():
     psi = gu.zeros()
     rels = [gu.mg_cycle(psi, want_residual=True) for _ in range(4)]
     assert all(b < a for a, b in zip(rels, rels[1:])) and rels[-1] < 0.5
+
+
+def _structured(G, N, nd, seed):
+    """psi[g, n, j, i] = f[g, j, i] d[g, n]: its moments are f times the moments of d, so the oracle
+    can evaluate the residual of a few ordinates of a field too large to hold on the host."""
+    f = random_field((G, N, N), seed=seed, lo=0.2, hi=1.0)
+    d = random_field((G, nd), seed=seed + 1, lo=0.5, hi=1.5)
+    return f, d
+
+
+def _device_product(f, d):
+    import torch
+    fd = torch.as_tensor(f, device="cuda")
+    dd = torch.as_tensor(d, device="cuda")
+    return fd[:, None, :, :] * dd[:, :, None, None]
+
+
+def _subquad(q, sel):
+    return {"mu": q["mu"][sel], "nu": q["nu"][sel], "p": q["p"][sel], "na": q["na"]}
+
+
+def test_c2_fullsize_residual_sampled():
+    """The largest workload: 512 x 512 nodes, p = 3, 2048 ordinates, 4 groups with P1 scattering,
+    2^31 DOF (offsets past 32 bits).  float64 residual of a structured psi on one ordinate of every
+    face and all groups, against the oracle."""
+    import sys
+    import torch
+    from oracle.quadrature import quadrature
+    from oracle.transport import emission_from_moments, moments
+    from paper_2301_09991_amd import ctf
+    w = WORKLOADS["c2_mfma_p1"]
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G, scatter_order=1,
+                             discretisation=ctf.CONVFEM_PG, precision=ctf.FP64)
+    print("c2 full size: creating the problem", file=sys.stderr, flush=True)
+    gp = ctf.Problem(cfg, st, ss, src)
+    q = quadrature(w.na)
+    nd = len(q["mu"])
+    f, d = _structured(w.G, w.N, nd, seed=31)
+    psi = _device_product(f, d)
+    out = gp.empty()
+    print("c2 full size: residual", file=sys.stderr, flush=True)
+    gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+    na2 = w.na * w.na
+    sel = np.array([fc * na2 + (fc * 97) % na2 for fc in range(8)])
+    got = out[:, torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    del psi, out, gp
+    torch.cuda.empty_cache()
+    Phi = f[:, None, :, :] * moments(d[:, :, None, None], q)
+    qs = _subquad(q, sel)
+    em = emission_from_moments(Phi, qs, ss, src)
+    h = w.L / w.N
+    ref = pg_residual(f[:, None, :, :] * d[:, sel, None, None], em, st, qs, h, h, w.p, (VACUUM,) * 4)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_c4_fullsize_upwind_residual_sampled():
+    """The learned-correction workload at full size (1024 x 1024 nodes, 512 ordinates, L = 32),
+    upwind discretisation: float64 residual of a structured psi on sampled ordinates."""
+    import sys
+    import torch
+    from oracle.quadrature import quadrature
+    from oracle.transport import emission_from_moments, moments, upwind_residual
+    from paper_2301_09991_amd import ctf
+    w = WORKLOADS["c4_learned"]
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G, scatter_order=0,
+                             discretisation=ctf.UPWIND, precision=ctf.FP64)
+    print("c4 full size: creating the problem", file=sys.stderr, flush=True)
+    gp = ctf.Problem(cfg, st, ss, src)
+    q = quadrature(w.na)
+    nd = len(q["mu"])
+    f, d = _structured(w.G, w.N, nd, seed=41)
+    psi = _device_product(f, d)
+    out = gp.empty()
+    print("c4 full size: residual", file=sys.stderr, flush=True)
+    gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+    na2 = w.na * w.na
+    sel = np.array([fc * na2 + (fc * 13) % na2 for fc in range(8)])
+    got = out[:, torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    del psi, out, gp
+    torch.cuda.empty_cache()
+    Phi = f[:, None, :, :] * moments(d[:, :, None, None], q)
+    qs = _subquad(q, sel)
+    em = emission_from_moments(Phi, qs, ss, src)
+    h = w.L / w.N
+    ref = upwind_residual(f[:, None, :, :] * d[:, sel, None, None], em, st, qs, h, h, (VACUUM,) * 4)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
