@@ -270,8 +270,10 @@ int ctf_cnn_sample(ctf_problem* prob, double* psi, const double* psi_star, float
                    float* target, double* scale);
 
 /* In-library kernel timers (HIP events recorded on the problem's stream around each launch of a
- * kernel class).  ctf_timing_enable(prob, 1, cap) synchronises, clears the counters and records
- * at most cap launches per class from then on; (prob, 0, 0) stops recording.
+ * kernel class).  ctf_timing_enable(prob, 1, cap, mask) synchronises, clears the counters and
+ * records at most cap launches per class from then on, for the classes whose bit (1u << class) is
+ * set in mask (0: every class; each recorded launch adds two event records to the stream, so
+ * timing only the classes of interest keeps the overhead small); (prob, 0, 0, 0) stops recording.
  * ctf_timing_read synchronises and returns the summed event time (ms) of the recorded launches
  * of one class, their count, and how many launches were not recorded for lack of capacity. */
 enum {
@@ -291,7 +293,7 @@ enum {
   CTF_T_PGK32,         /* same, float32 */
   CTF_T_COUNT
 };
-int ctf_timing_enable(ctf_problem* prob, int on, int capacity);
+int ctf_timing_enable(ctf_problem* prob, int on, int capacity, unsigned class_mask);
 int ctf_timing_read(ctf_problem* prob, int cls, double* total_ms, int* launches, int* dropped);
 
 /* Thread-local description of the last error ("" if none). */

@@ -145,6 +145,7 @@ struct ctf_problem {
   // in-library kernel timers: per kernel class, pairs of events recorded around each launch
   bool timing = false;
   int timing_cap = 0;
+  unsigned timing_mask = ~0u;   // bit c set: class c is timed
   std::vector<hipEvent_t> ev[CTF_T_COUNT];
   int ev_used[CTF_T_COUNT] = {};
   int ev_dropped[CTF_T_COUNT] = {};
@@ -174,7 +175,7 @@ struct Timed {
   ctf_problem* P;
   int cls, slot = -1;
   Timed(ctf_problem* p, int c) : P(p), cls(c) {
-    if (!P->timing) return;
+    if (!P->timing || !((P->timing_mask >> cls) & 1u)) return;
     if (P->ev_used[cls] >= P->timing_cap) {
       ++P->ev_dropped[cls];
       return;
@@ -1418,8 +1419,9 @@ int ctf_cnn_sample(ctf_problem* P, double* psi, const double* psi_star, float* f
   return CTF_OK;
 }
 
-int ctf_timing_enable(ctf_problem* P, int on, int capacity) {
+int ctf_timing_enable(ctf_problem* P, int on, int capacity, unsigned class_mask) {
   if (!P || capacity < 0) return fail(CTF_EINVAL, "bad argument");
+  P->timing_mask = class_mask ? class_mask : ~0u;
   CTF_HIP(hipStreamSynchronize(P->stream));
   P->timing = false;
   for (int c = 0; c < CTF_T_COUNT; ++c) {

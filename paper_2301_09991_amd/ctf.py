@@ -105,7 +105,7 @@ def load():
         "ctf_solve": (I, [P, P, D, I, ctypes.POINTER(SolveInfo)]),
         "ctf_norm": (I, [P, P, ctypes.POINTER(D)]),
         "ctf_last_error": (ctypes.c_char_p, []),
-        "ctf_timing_enable": (I, [P, I, I]),
+        "ctf_timing_enable": (I, [P, I, I, ctypes.c_uint]),
         "ctf_timing_read": (I, [P, I, ctypes.POINTER(D), ctypes.POINTER(I), ctypes.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
@@ -330,8 +330,12 @@ class Problem:
                 "history": hist[:n].copy() if history_len else None,
                 "cnn_applied": info.cnn_applied, "cnn_rejected": info.cnn_rejected}
 
-    def timing_enable(self, on=True, capacity=4096):
-        _check(self.lib.ctf_timing_enable(self.handle, int(on), capacity if on else 0))
+    def timing_enable(self, on=True, capacity=4096, classes=None):
+        """Record HIP events around the launches of the named kernel classes (default: all)."""
+        mask = 0
+        for name in classes or ():
+            mask |= 1 << TIMER_CLASSES.index(name)
+        _check(self.lib.ctf_timing_enable(self.handle, int(on), capacity if on else 0, mask))
 
     def timing_read(self):
         """{class: (total_ms, launches, dropped)} of the recorded kernel launches."""
