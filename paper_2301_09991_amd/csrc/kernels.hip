@@ -578,11 +578,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
 //   D  output row r - 4P (y-passes over registers)
 // psi, Psi and k rows live in LDS rings deep enough for every later stage that reads them (the
 // centre values of row r - 4P included); the y-pass windows rotate with the unrolled step.
-template <int P>
 __device__ __forceinline__ int ring_slot(int row, int depth) {
   const int m = row % depth;
   return m < 0 ? m + depth : m;
 }
+// slot of the row `off` rows above the row in slot s (0 <= off < depth)
+__device__ __forceinline__ int ring_back(int s, int off, int depth) { return s >= off ? s - off : s - off + depth; }
+__device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == depth ? 0 : s + 1; }
 
 template <int P, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
@@ -593,10 +595,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   constexpr int GR = 3 * P + 1;         // Psi rows kept (r - 4P .. r - P)
   constexpr int KR = 2 * P + 1;         // k rows kept (r - 4P .. r - 2P)
   constexpr int OW = kStripW - 4 * P;   // columns written per strip
-  // x and y components side by side, so that both are addressed from one base
+  // x and y components side by side, so that both are addressed from one base; Psi and k rows
+  // carry P unused entries on either side, so that every lane's taps stay inside the array
+  // (lanes whose results are not used read those entries instead of branching around the taps)
+  constexpr int GW = kStripW + 2 * P;
   __shared__ T s_psi[PR][RW];
-  __shared__ T s_g[GR][2][kStripW];   // Psi_x, Psi_y
-  __shared__ T s_k[KR][2][kStripW];   // k_x, k_y (columns outside the domain: the k halo copy)
+  __shared__ T s_g[GR][2][GW];   // Psi_x, Psi_y of lane l at index P + l
+  __shared__ T s_k[KR][2][GW];   // k_x, k_y (columns outside the domain: the k halo copy)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
   const StripBlock sb = strip_block();
@@ -624,12 +629,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const bool zx1 = (lc1 < 0 && (a.bc_vac & 1) && mu > T(0)) || (lc1 >= n && (a.bc_vac & 2) && mu < T(0));
   const int col = c0 + lane;
   const bool writer = lane >= 2 * P && lane < kStripW - 2 * P && col < n;
-  const bool kvalid = lane >= P && lane < kStripW - P;
-  const bool cvalid = lane >= P && lane < kStripW - P;
   // strips that reach past the domain copy k of the nearest interior column into those columns
   const bool edge_strip = c0 < 0 || c0 + kStripW > n;
-  const bool outside = col < 0 || col >= n;
-  const int kcl = clampi(col, 0, n - 1) - c0;   // lane of the nearest interior column
+  const int kcl = clampi(col, 0, n - 1) - c0;   // lane of the nearest interior column (own lane inside)
+  const int hidx = lane < 2 * P ? kStripW + lane : lane;   // halo lanes also write the P columns past 64
   const int yend = min(y0 + a.strip_h, n);
   const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
@@ -659,21 +662,24 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg);
+  // ring slots of psi row r, Psi row r - P and k row r - 2P, advanced every step
+  int sp = ring_slot(rbeg, PR), sg = ring_slot(rbeg - P, GR), sk = ring_slot(rbeg - 2 * P, KR);
   for (int r0 = rbeg; r0 < rend; r0 += W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       const int r = r0 + t;
       if (r >= rend) break;
-      T* const prow = s_psi[ring_slot<P>(r, PR)];
+      T* const prow = s_psi[sp];
       const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-      prow[lane] = (zy || zx0) ? T(0) : p0;
-      if (lane < 2 * P) prow[kStripW + lane] = (zy || zx1) ? T(0) : p1;
+      const T v0 = (zy || zx0) ? T(0) : p0, v1 = (zy || zx1) ? T(0) : p1;
+      prow[lane] = v0;
+      prow[hidx] = lane < 2 * P ? v1 : v0;   // other lanes rewrite their own value
       const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
       load_row(r + 1);   // past the last row this reloads a clamped row, unused
       __syncthreads();
       // A: Psi of row r - P
-      T* const gxr = s_g[ring_slot<P>(r - P, GR)][0];
-      T* const gyr = s_g[ring_slot<P>(r - P, GR)][1];
+      T* const gxr = &s_g[sg][0][P];
+      T* const gyr = &s_g[sg][1][P];
       {
         T xd = 0, xm = 0;
 #pragma unroll
@@ -691,36 +697,30 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       // B: k of row r - 2P
       {
         T mx = 0, my = 0;
-        if (kvalid) {
 #pragma unroll
-          for (int u = 0; u < W; ++u) {
-            mx += cm[u] * gxr[lane - P + u];
-            my += cm[u] * gyr[lane - P + u];
-          }
+        for (int u = 0; u < W; ++u) {
+          mx += cm[u] * gxr[lane - P + u];
+          my += cm[u] * gyr[lane - P + u];
         }
         wMx[t] = mx;
         wMy[t] = my;
         const int rk = r - 2 * P;
         if (rk >= 0 && rk < n) {
-          const int gs = ring_slot<P>(rk, GR);
-          const T px = s_g[gs][0][lane], py = s_g[gs][1][lane];
+          const int gs = ring_back(sg, P, GR);
+          const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
           const T rx = ar * mu * (yrot(wMx, cm, t) - px);
           const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-          T(&kr)[2][kStripW] = s_k[ring_slot<P>(rk, KR)];
-          kr[0][lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
-          kr[1][lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          T* const k0r = &s_k[sk][0][P];
+          T* const k1r = &s_k[sk][1][P];
+          k0r[lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
+          k1r[lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
           if (edge_strip) {
+            // columns outside the domain take k of the nearest interior column
             __syncthreads();
-            T ox = 0, oy = 0;
-            if (outside) {
-              ox = kr[0][kcl];
-              oy = kr[1][kcl];
-            }
+            const T ox = k0r[kcl], oy = k1r[kcl];
             __syncthreads();
-            if (outside) {
-              kr[0][lane] = ox;
-              kr[1][lane] = oy;
-            }
+            k0r[lane] = ox;
+            k1r[lane] = oy;
           }
         }
       }
@@ -728,23 +728,21 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       // C: x-passes of row s = r - 3P (k of the clamped row and columns)
       {
         const int srow = r - 3 * P;
-        const T* const sp = s_psi[ring_slot<P>(srow, PR)];
-        const int ks = ring_slot<P>(clampi(srow, 0, n - 1), KR);
-        const T* const kxr = s_k[ks][0];
-        const T* const kyr = s_k[ks][1];
+        const T* const spr = s_psi[ring_back(sp, 3 * P, PR)];
+        const int ks = (srow >= 0 && srow < n) ? ring_back(sk, P, KR) : ring_slot(clampi(srow, 0, n - 1), KR);
+        const T* const kxr = &s_k[ks][0][P];
+        const T* const kyr = &s_k[ks][1][P];
         T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0;
-        if (cvalid) {
 #pragma unroll
-          for (int u = 0; u < W; ++u) {
-            const T v = sp[lane + u];
-            const T kv = kxr[lane - P + u], qv = kyr[lane - P + u];
-            a1x += ck[u] * v;
-            a2x += ck[u] * (kv * v);
-            a3x += ck[u] * kv;
-            a1y += cm[u] * v;
-            a2y += cm[u] * (qv * v);
-            a3y += cm[u] * qv;
-          }
+        for (int u = 0; u < W; ++u) {
+          const T v = spr[lane + u];
+          const T kv = kxr[lane - P + u], qv = kyr[lane - P + u];
+          a1x += ck[u] * v;
+          a2x += ck[u] * (kv * v);
+          a3x += ck[u] * kv;
+          a1y += cm[u] * v;
+          a2y += cm[u] * (qv * v);
+          a3y += cm[u] * qv;
         }
         wA1x[t] = a1x;
         wA2x[t] = a2x;
@@ -756,10 +754,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       // D: output row r - 4P
       const int o = r - 4 * P;
       if (o >= y0 && writer) {
-        const int gs = ring_slot<P>(o, GR), ks = ring_slot<P>(o, KR);
-        const T px = s_g[gs][0][lane], py = s_g[gs][1][lane];
-        const T psc = s_psi[ring_slot<P>(o, PR)][lane + P];
-        const T kxc = s_k[ks][0][lane], kyc = s_k[ks][1][lane];
+        const int gs = ring_back(sg, 3 * P, GR), ks = ring_back(sk, 2 * P, KR);
+        const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
+        const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
+        const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
         const T dx = kxc * yrot(wA1x, cm, t) + yrot(wA2x, cm, t) - psc * yrot(wA3x, cm, t);
         const T dy = kyc * yrot(wA1y, ck, t) + yrot(wA2y, ck, t) - psc * yrot(wA3y, ck, t);
         const size_t ro = base + size_t(o) * n;
@@ -777,6 +775,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         }
       }
       __syncthreads();   // the next step overwrites ring slots read above
+      sp = ring_next(sp, PR);
+      sg = ring_next(sg, GR);
+      sk = ring_next(sk, KR);
     }
   }
   if (a.partial) {
