@@ -855,6 +855,7 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
   const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
   const int iu = mu > T(0) ? i - 1 : i + 1;
   const bool xin_dom = iu >= 0 && iu < n;
+  const int iuc = clampi(iu, 0, n - 1);
   const bool xvac = mu > T(0) ? (bc_vac & 1) : (bc_vac & 2);
   const bool yvac = nu > T(0) ? (bc_vac & 4) : (bc_vac & 8);
   const T amu = tabs(mu) / h, anu = tabs(nu) / h;
@@ -872,26 +873,36 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
   const bool down = nu > T(0);          // upwind row j - 1: walk with increasing j
   const int j0 = down ? jb : je - 1;
   const int ju0 = down ? j0 - 1 : j0 + 1;
-  bool prev_in = ju0 >= 0 && ju0 < n;
-  T eprev = (XMODE != 2 && prev_in) ? value(ju0, i) : T(0);
+  const bool prev_in = ju0 >= 0 && ju0 < n;
+  // every load of the thread's rows first (rows past the strip end clamped to its last row, so
+  // all loads are in bounds and independent), then the sweep itself
+  T ec[kCorrRows], ex[kCorrRows], rh[kCorrRows], sg[kCorrRows], av[kCorrRows];
 #pragma unroll
   for (int t = 0; t < kCorrRows; ++t) {
-    const int j = down ? j0 + t : j0 - t;
-    if (j < jb || j >= je) break;
+    const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
     const size_t cell = size_t(j) * n + i;
-    T ec = 0, ex = 0;
-    if (XMODE != 2) {
-      ec = value(j, i);
-      ex = xin_dom ? value(j, iu) : (xvac ? T(0) : ec);
-    }
-    const T ey = prev_in ? eprev : (yvac ? T(0) : ec);
-    const T sig = sigma[cell];
-    const T r = rhs[plane + cell] - amu * (ec - ex) - anu * (ec - ey) - sig * ec;
-    const T enew = ec + r / (amu + anu + sig);
-    if (acc) acc[plane + cell] += enew;
+    ec[t] = value(j, i);
+    ex[t] = value(j, iuc);
+    rh[t] = rhs[plane + cell];
+    sg[t] = sigma[cell];
+    av[t] = acc ? acc[plane + cell] : T(0);
+  }
+  T eprev = value(clampi(ju0, 0, n - 1), i);   // used only if that row is inside the domain
+  const int rows = je - jb;
+#pragma unroll
+  for (int t = 0; t < kCorrRows; ++t) {
+    if (t >= rows) break;
+    const int j = down ? j0 + t : j0 - t;
+    const size_t cell = size_t(j) * n + i;
+    const T c = ec[t];
+    const T x = xin_dom ? ex[t] : (xvac ? T(0) : c);
+    const T y = (t > 0 || prev_in) ? eprev : (yvac ? T(0) : c);
+    const T sig = sg[t];
+    const T r = rh[t] - amu * (c - x) - anu * (c - y) - sig * c;
+    const T enew = c + r / (amu + anu + sig);
+    if (acc) acc[plane + cell] = av[t] + enew;
     else xout[plane + cell] = enew;
-    eprev = ec;
-    prev_in = true;
+    eprev = c;
   }
 }
 
