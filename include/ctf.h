@@ -77,6 +77,11 @@ typedef struct ctf_config {
   double cnn_max_growth; /* the correction is switched off once a cycle applying it multiplies the
                             residual by more than this (default 1: it must not grow) */
   int cnn_max_uses;      /* steps of a solve that may apply the correction (default 2) */
+  int hemisphere;        /* 1: only the ordinates with xi > 0 (faces 0..3, n_dir = 4 na^2), weights
+                            doubled (normalised to 4 pi over the half set).  The 2D equations see
+                            only (mu, nu), and every ordinate has a mirror with xi < 0, equal
+                            (mu, nu) and equal weight, so the flux is even in xi and the result on
+                            the kept ordinates equals the full set's; half the work.  Default 0. */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;

@@ -57,6 +57,7 @@ int validate(const ctf_config* c) {
   if (c->cnn_level >= 0 && !(c->cnn_max_growth > 0.0)) return fail(CTF_EINVAL, "cnn_max_growth > 0");
   if (c->cnn_level >= 0 && c->ngroups != 1)
     return fail(CTF_EUNSUPPORTED, "the learned correction supports one energy group");
+  if (c->hemisphere != 0 && c->hemisphere != 1) return fail(CTF_EINVAL, "hemisphere 0 or 1");
   return CTF_OK;
 }
 
@@ -256,7 +257,7 @@ void init_dims(ctf_problem* P) {
   int n = c.n, na = c.na;
   double h = c.length / c.n;
   for (int l = 0; l < P->L; ++l) {
-    P->dims[l] = LevelDims{n, 8 * na * na, na, c.ngroups, h, nullptr};
+    P->dims[l] = LevelDims{n, (c.hemisphere ? 4 : 8) * na * na, na, c.ngroups, h, nullptr};
     n /= 2;
     na = na > 1 ? na / 2 : 1;
     h *= 2.0;
@@ -381,14 +382,14 @@ template <typename T>
 int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsrc, int xmode,
                       const T* rhs, int nsweeps, T* bufa, T* bufb, T* acc, const T** result,
                       T* final = nullptr) {
-  const int nac = (l + 1 < P->L) ? P->dims[l + 1].na : 1;
+  const int ndc = (l + 1 < P->L) ? P->dims[l + 1].nd : 1;   // ordinates of the next coarser level
   const T* cur = xsrc;
   int mode = xmode;
   for (int s = 0; s < nsweeps; ++s) {
     const bool last = s == nsweeps - 1;
     T* dst = (last && final) ? final : ((s % 2 == 0) ? bufa : bufb);
     Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
-    CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, nac, rhs, dst,
+    CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, ndc, rhs, dst,
                                         (last && acc) ? acc : nullptr, P->stream, P->corr_block));
     cur = dst;
     mode = 0;
@@ -699,6 +700,7 @@ void ctf_default_config(ctf_config* c) {
   c->cnn_level = -1;
   c->cnn_max_growth = 1.0;
   c->cnn_max_uses = 2;
+  c->hemisphere = 0;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -764,7 +766,7 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   const size_t nc0 = size_t(cfg->n) * cfg->n;
   const int nl = cfg->scatter_order + 1;
   // quadrature per level
-  P->quad[0] = build_quadrature(cfg->na);
+  P->quad[0] = build_quadrature(cfg->na, cfg->hemisphere ? 4 : 8);
   for (int l = 1; l < P->L; ++l) P->quad[l] = coarsen_quadrature(P->quad[l - 1]);
   std::vector<std::vector<double>> hd(P->L);
   std::vector<std::vector<float>> hf(P->L);
@@ -971,7 +973,7 @@ int ctf_prolong(ctf_problem* P, int level, const double* coarse, double* fine) {
   int rc = check_level(P, level);
   if (rc) return rc;
   if (level + 1 >= P->L) return fail(CTF_EINVAL, "no coarser level");
-  CTF_HIP(launch_prolong<double>(P->ld(level), P->dims[level + 1].na, coarse, fine, P->stream));
+  CTF_HIP(launch_prolong<double>(P->ld(level), P->dims[level + 1].nd, coarse, fine, P->stream));
   return CTF_OK;
 }
 

@@ -19,11 +19,13 @@ constexpr int kMaxLevels = 16;
 // ---- host-side setup (setup.cpp) ---------------------------------------------------------------
 struct Quadrature {
   int na = 0;
-  std::vector<double> mu, nu, xi, w;  // n_dir each, w sums to 4 pi
+  int faces = 8;                       // 8, or 4 (the xi > 0 half)
+  std::vector<double> mu, nu, xi, w;  // n_dir = faces * na^2 each, w sums to 4 pi
 };
 
-// Finest ordinates of the octahedral patch set (section "Discrete Ordinates").
-Quadrature build_quadrature(int na);
+// Finest ordinates of the octahedral patch set (section "Discrete Ordinates"); faces = 4 keeps
+// the faces with xi > 0 (the weights, normalised to 4 pi, are then twice the full set's).
+Quadrature build_quadrature(int na, int faces = 8);
 // Coarse ordinates: children patches added (section "Space-Angle Multigrid").
 Quadrature coarsen_quadrature(const Quadrature& q);
 // Parent ordinate of fine ordinate n on a face grid of na x na (identity once na == 1).
@@ -130,11 +132,11 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
                               int nmomE, T* out, int mode, T sign, const T* rhs, hipStream_t s);
 
 // Correction sweep e_new = e + (rhs - A_up e - sigma_t e) / d on one level.
-//   xmode 0: e from x_in;  1: e = UpSamp(x_coarse) (x_in is the level+1 array, nac its na);
+//   xmode 0: e from x_in;  1: e = UpSamp(x_coarse) (x_in is the level+1 array, ndc its n_dir);
 //   2: e = 0.   psi_acc != null: psi_acc += e_new instead of writing x_out.
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
-                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
+                                    int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
                                     int block = 256);
 
 template <typename T>
@@ -142,7 +144,7 @@ hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const
                            T* coarse, hipStream_t s);
 
 template <typename T>
-hipError_t launch_prolong(const LevelData<T>& Lf, int nac, const T* coarse, T* fine, hipStream_t s);
+hipError_t launch_prolong(const LevelData<T>& Lf, int ndc, const T* coarse, T* fine, hipStream_t s);
 
 // partial[b] = sum over block b of w_n h^2 v^2, then out[0] = sum of partials (fixed order).
 template <typename T>

@@ -838,7 +838,7 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
 constexpr int kCorrRows = 8;
 template <typename T, int XMODE>
 __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
-                                                         const T* __restrict__ xin, int nac,
+                                                         const T* __restrict__ xin, int ndc,
                                                          const T* __restrict__ rhs,
                                                          T* __restrict__ xout, T* __restrict__ acc) {
   if (idle(L.dims.active)) return;
@@ -864,7 +864,7 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
   const int nc = n >> 1;
   const T* __restrict__ src = xin;
   if (XMODE == 1)
-    src = xin + (size_t(g) * (size_t(8) * (nac * nac)) + parent_dir_dev(dir, L.dims.na)) * (size_t(nc) * nc);
+    src = xin + (size_t(g) * ndc + parent_dir_dev(dir, L.dims.na)) * (size_t(nc) * nc);
   auto value = [&](int jj, int ii) -> T {
     if (XMODE == 0) return xin[plane + size_t(jj) * n + ii];
     if (XMODE == 1) return src[size_t(jj >> 1) * nc + (ii >> 1)];
@@ -938,7 +938,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(LevelData<T> Lf, int nac,
+__global__ __launch_bounds__(kBlock) void k_prolong(LevelData<T> Lf, int ndc,
                                                      const T* __restrict__ coarse,
                                                      T* __restrict__ fine) {
   const int n = Lf.dims.n, nd = Lf.dims.nd;
@@ -949,7 +949,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(LevelData<T> Lf, int nac,
   const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
   const int j = cell / n, i = cell - j * n;
   const int nc = n >> 1;
-  fine[idx] = coarse[(size_t(g) * (size_t(8) * nac * nac) + parent_dir_dev(dir, Lf.dims.na)) *
+  fine[idx] = coarse[(size_t(g) * ndc + parent_dir_dev(dir, Lf.dims.na)) *
                          (size_t(nc) * nc) + size_t(j >> 1) * nc + (i >> 1)];
 }
 
@@ -1205,18 +1205,18 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
-                                    int nac, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
+                                    int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
   if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
   const int n = L.dims.n;
   const int rows_per_block = (block / 64) * kCorrRows;
   const unsigned nb = unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block);
   const dim3 grid(nb, L.dims.nd, L.dims.G), blk(block);
   if (xmode == 0)
-    hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
+    hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
   else if (xmode == 1)
-    hipLaunchKernelGGL((k_upwind_corr<T, 1>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
+    hipLaunchKernelGGL((k_upwind_corr<T, 1>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
   else
-    hipLaunchKernelGGL((k_upwind_corr<T, 2>), grid, blk, 0, s, L, bc_vac, x_in, nac, rhs, x_out, psi_acc);
+    hipLaunchKernelGGL((k_upwind_corr<T, 2>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
   return hipGetLastError();
 }
 
@@ -1229,9 +1229,9 @@ hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const
 }
 
 template <typename T>
-hipError_t launch_prolong(const LevelData<T>& Lf, int nac, const T* coarse, T* fine, hipStream_t s) {
+hipError_t launch_prolong(const LevelData<T>& Lf, int ndc, const T* coarse, T* fine, hipStream_t s) {
   const dim3 grid(nblocks(size_t(Lf.dims.n) * Lf.dims.n), Lf.dims.nd, Lf.dims.G);
-  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, Lf, nac, coarse, fine);
+  hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, Lf, ndc, coarse, fine);
   return hipGetLastError();
 }
 

@@ -75,18 +75,19 @@ void patch(double sx, double sy, double sz, double s0, double s1, double t0, dou
 
 }  // namespace
 
-Quadrature build_quadrature(int na) {
+Quadrature build_quadrature(int na, int faces) {
   std::vector<double> gx, gw;
   gauss_legendre(kPatchGauss, gx, gw);
-  const int nd = 8 * na * na;
+  const int nd = faces * na * na;
   Quadrature q;
   q.na = na;
+  q.faces = faces;
   q.mu.resize(nd);
   q.nu.resize(nd);
   q.xi.resize(nd);
   q.w.resize(nd);
   double total = 0.0;
-  for (int f = 0; f < 8; ++f) {
+  for (int f = 0; f < faces; ++f) {
     const double sx = (f & 1) ? -1.0 : 1.0, sy = (f & 2) ? -1.0 : 1.0, sz = (f & 4) ? -1.0 : 1.0;
     for (int a = 0; a < na; ++a)
       for (int b = 0; b < na; ++b) {
@@ -107,14 +108,15 @@ Quadrature build_quadrature(int na) {
 }
 
 Quadrature coarsen_quadrature(const Quadrature& q) {
-  const int na = q.na, nc = na > 1 ? na / 2 : 1, ndc = 8 * nc * nc;
+  const int na = q.na, nc = na > 1 ? na / 2 : 1, ndc = q.faces * nc * nc;
   Quadrature c;
   c.na = nc;
+  c.faces = q.faces;
   c.w.assign(ndc, 0.0);
   c.mu.assign(ndc, 0.0);
   c.nu.assign(ndc, 0.0);
   c.xi.assign(ndc, 0.0);
-  for (int n = 0; n < 8 * na * na; ++n) {
+  for (int n = 0; n < q.faces * na * na; ++n) {
     const int N = parent_dir(n, na);
     c.w[N] += q.w[n];
     c.mu[N] += q.w[n] * q.mu[n];

@@ -167,3 +167,22 @@ def test_pg_converges_on_optically_thick_cells():
     prob = _c0_small(N=16, na=2, disc=PG, L=16.0, p=2)
     psi, hist, ok = solve(prob, rtol=1e-9, max_cycles=120)
     assert ok, hist[-5:]
+
+
+@pytest.mark.parametrize("disc", [UPWIND, PG])
+def test_solution_is_even_in_xi(disc):
+    """In 2D the equations see only (mu, nu); every ordinate of face f (xi > 0) has a mirror on
+    face f + 4 with the same (mu, nu) and weight, so the cycle keeps psi even in xi (the reading
+    behind solving on the xi > 0 half with doubled weights)."""
+    from workloads import Workload
+    w = Workload("mirror", 16, 16.0, 2, 2, 1, 4, "iso", "box_center8", (0.3, 0.9), 3)
+    st, ss, src = make_inputs(w)
+    prob = Problem(w.N, w.L, w.p, w.na, st, ss, src, disc=disc)
+    q = prob.quad
+    half = 4 * w.na * w.na
+    assert np.array_equal(q["mu"][:half], q["mu"][half:]) and np.array_equal(q["nu"][:half], q["nu"][half:])
+    assert np.allclose(q["p"][:half], q["p"][half:], rtol=1e-14, atol=0)
+    psi = np.zeros(prob.shape())
+    for _ in range(4):
+        psi = sawtooth_cycle(prob, psi)
+    assert np.abs(psi[:, :half] - psi[:, half:]).max() <= 1e-13 * np.abs(psi).max()
