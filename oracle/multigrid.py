@@ -40,15 +40,15 @@ def harmonic_coarsen(sig):
 
 
 class Level:
-    def __init__(self, N, h, quad, sigma_t):
-        self.N, self.h, self.quad, self.sigma_t = N, h, quad, sigma_t
+    def __init__(self, N, h, quad, sigma_t, sigma_s):
+        self.N, self.h, self.quad, self.sigma_t, self.sigma_s = N, h, quad, sigma_t, sigma_s
 
 
 class Problem:
     """A fixed-source problem on the square [0, L]^2 with N x N nodes (h = L / N)."""
 
     def __init__(self, N, L, p, na, sigma_t, sigma_s, source, bc=(VACUUM,) * 4, disc=PG,
-                 n_jacobi=2, n_pg=None, max_levels=0, beta_pg=3.0, quad=None):
+                 n_jacobi=2, n_pg=None, max_levels=0, beta_pg=3.0, quad=None, coupled=False):
         self.N, self.L, self.p, self.na = N, L, p, na
         self.h = L / N
         self.sigma_t = np.asarray(sigma_t, dtype=float)
@@ -60,13 +60,17 @@ class Problem:
         self.n_pg = n_jacobi if n_pg is None else n_pg
         self.beta_pg = beta_pg
         self.k_frozen = None
+        # extension (the paper is silent): correction sweeps that include the scattering of the
+        # correction on every level
+        self.coupled = coupled
         q0 = quad if quad is not None else qd.quadrature(na)
-        self.levels = [Level(N, self.h, q0, self.sigma_t)]
+        self.levels = [Level(N, self.h, q0, self.sigma_t, self.sigma_s)]
         while True:
             lv = self.levels[-1]
             if lv.N % 2 or lv.N <= 2 or (max_levels and len(self.levels) >= max_levels):
                 break
-            self.levels.append(Level(lv.N // 2, 2 * lv.h, qd.coarsen(lv.quad), harmonic_coarsen(lv.sigma_t)))
+            self.levels.append(Level(lv.N // 2, 2 * lv.h, qd.coarsen(lv.quad), harmonic_coarsen(lv.sigma_t),
+                                     harmonic_coarsen(lv.sigma_s)))
 
     @property
     def quad(self):
@@ -126,11 +130,17 @@ def upsample(e_c, lf):
 
 def upwind_jacobi(prob, level, e, s, nsweeps, beta=1.0):
     """e <- e + (s - A_up e - sigma_t e) / (beta d) on one level (eq. matrix_full with the upwind
-    system; beta = 1 on every grid for the upwind scheme)."""
+    system; beta = 1 on every grid for the upwind scheme).
+
+    With ``prob.coupled`` (an extension; the paper is silent) the sweep also adds the scattering
+    of the correction, the emission of e with no external source on the level's own ordinates and
+    (harmonically averaged) sigma_s: e <- e + (s + S e - A_up e - sigma_t e) / (beta d), d as above."""
     lv = prob.levels[level]
     d = beta * upwind_diagonal(lv.sigma_t, lv.quad, lv.h, lv.h)
     for _ in range(nsweeps):
         r = s - upwind_advection(e, lv.quad, lv.h, lv.h, prob.bc) - lv.sigma_t[:, None] * e
+        if prob.coupled:
+            r = r + emission(e, lv.quad, lv.sigma_s, np.zeros_like(lv.sigma_t))
         e = e + r / d
     return e
 
