@@ -82,6 +82,11 @@ typedef struct ctf_config {
                             only (mu, nu), and every ordinate has a mirror with xi < 0, equal
                             (mu, nu) and equal weight, so the flux is even in xi and the result on
                             the kept ordinates equals the full set's; half the work.  Default 0. */
+  int coupled_scatter;   /* 1: every correction sweep on every level adds the scattering of the
+                            correction (emission of e with the level's 2 x 2 harmonic sigma_s, no
+                            external source), so the coarse levels correct the scattering modes too;
+                            the discrete equations and their solution are unchanged.  An extension
+                            (the paper's sweeps are transport-only).  Default 0. */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;
@@ -296,6 +301,7 @@ enum {
   CTF_T_CNN,           /* learned correction: features, network, application */
   CTF_T_PGK64,         /* stored non-linear PG diffusivities (their own pass), float64 */
   CTF_T_PGK32,         /* same, float32 */
+  CTF_T_CSCAT,         /* moments + emission of the corrections (coupled_scatter) */
   CTF_T_COUNT
 };
 int ctf_timing_enable(ctf_problem* prob, int on, int capacity, unsigned class_mask);

@@ -58,6 +58,7 @@ int validate(const ctf_config* c) {
   if (c->cnn_level >= 0 && c->ngroups != 1)
     return fail(CTF_EUNSUPPORTED, "the learned correction supports one energy group");
   if (c->hemisphere != 0 && c->hemisphere != 1) return fail(CTF_EINVAL, "hemisphere 0 or 1");
+  if (c->coupled_scatter != 0 && c->coupled_scatter != 1) return fail(CTF_EINVAL, "coupled_scatter 0 or 1");
   return CTF_OK;
 }
 
@@ -105,6 +106,8 @@ struct ctf_problem {
   float* eb_f[kMaxLevels];
   // finest-level data
   double* sigma_s = nullptr;
+  double* sigs_d[kMaxLevels] = {};   // sigma_s per level (level 0: sigma_s; coarser: 2 x 2 harmonic)
+  float* sigs_f[kMaxLevels] = {};
   double* source = nullptr;
   float* sigma_s_f = nullptr;
   double* phi = nullptr;
@@ -223,8 +226,14 @@ size_t layout(ctf_problem* P, char* base) {
   const bool need_k = cfg.discretisation != CTF_UPWIND;
   P->kx = need_k ? c.take<double>(P->dof(0)) : nullptr;
   P->ky = need_k ? c.take<double>(P->dof(0)) : nullptr;
+  P->sigs_d[0] = P->sigma_s;
+  for (int l = 1; l < P->L && cfg.coupled_scatter; ++l)
+    P->sigs_d[l] = c.take<double>(size_t(nl) * G * G * size_t(P->dims[l].n) * P->dims[l].n);
   if (mixed) {
     P->sigma_s_f = c.take<float>(size_t(nl) * G * G * nc0);
+    P->sigs_f[0] = P->sigma_s_f;
+    for (int l = 1; l < P->L && cfg.coupled_scatter; ++l)
+      P->sigs_f[l] = c.take<float>(size_t(nl) * G * G * size_t(P->dims[l].n) * P->dims[l].n);
     P->phi_f = c.take<float>(3 * G * nc0);
     P->E_f = c.take<float>(3 * G * nc0);
     P->kx_f = need_k ? c.take<float>(P->dof(0)) : nullptr;
@@ -375,9 +384,25 @@ int wnorm64(ctf_problem* P, int level, const double* v, double* out_host) {
   return read_norm(P, out_host);
 }
 
+// per-precision views of the problem's level data and moment / emission buffers
+template <typename T> LevelData<T> level_data(const ctf_problem* P, int l);
+template <> LevelData<double> level_data<double>(const ctf_problem* P, int l) { return P->ld(l); }
+template <> LevelData<float> level_data<float>(const ctf_problem* P, int l) { return P->lf(l); }
+template <typename T> T* phi_buffer(ctf_problem* P);
+template <> double* phi_buffer<double>(ctf_problem* P) { return P->phi; }
+template <> float* phi_buffer<float>(ctf_problem* P) { return P->phi_f; }
+template <typename T> T* emission_buffer(ctf_problem* P);
+template <> double* emission_buffer<double>(ctf_problem* P) { return P->E; }
+template <> float* emission_buffer<float>(ctf_problem* P) { return P->E_f; }
+template <typename T> const T* level_sigma_s(const ctf_problem* P, int l);
+template <> const double* level_sigma_s<double>(const ctf_problem* P, int l) { return P->sigs_d[l]; }
+template <> const float* level_sigma_s<float>(const ctf_problem* P, int l) { return P->sigs_f[l]; }
+
 // n upwind correction sweeps on level l: the first from (xmode, xsrc), result pointer returned;
 // acc != null: the last sweep adds into acc instead of writing a buffer; final != null: the last
-// sweep writes there.
+// sweep writes there.  With coupled_scatter every sweep adds the scattering of its input e (the
+// emission of e on the level, no external source; for the first sweep from the coarser level the
+// moments of UpSamp(e) are those of e on its own level, read at the parent cells).
 template <typename T>
 int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsrc, int xmode,
                       const T* rhs, int nsweeps, T* bufa, T* bufb, T* acc, const T** result,
@@ -388,9 +413,23 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
   for (int s = 0; s < nsweeps; ++s) {
     const bool last = s == nsweeps - 1;
     T* dst = (last && final) ? final : ((s % 2 == 0) ? bufa : bufb);
+    const T* Esc = nullptr;
+    if (P->cfg.coupled_scatter && mode != 2) {
+      Timed t(P, CTF_T_CSCAT);
+      const int nl = P->cfg.scatter_order + 1;
+      T* phi = phi_buffer<T>(P);
+      if (mode == 1)
+        CTF_HIP(launch_moments<T>(level_data<T>(P, l + 1), cur, phi, P->nmom, P->stream));
+      else
+        CTF_HIP(launch_moments<T>(L, cur, phi, P->nmom, P->stream));
+      CTF_HIP(launch_emission<T>(P->dims[l], phi, level_sigma_s<T>(P, l), nl, nullptr, emission_buffer<T>(P),
+                                 P->stream, mode == 1 ? 1 : 0));
+      Esc = emission_buffer<T>(P);
+    }
     Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
     CTF_HIP(launch_upwind_correction<T>(L, P->bc_vac, cur, mode, ndc, rhs, dst,
-                                        (last && acc) ? acc : nullptr, P->stream, P->corr_block));
+                                        (last && acc) ? acc : nullptr, P->stream, P->corr_block, Esc,
+                                        P->nmom));
     cur = dst;
     mode = 0;
   }
@@ -701,6 +740,7 @@ void ctf_default_config(ctf_config* c) {
   c->cnn_max_growth = 1.0;
   c->cnn_max_uses = 2;
   c->hemisphere = 0;
+  c->coupled_scatter = 0;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -789,15 +829,21 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
                      hipMemcpyDeviceToDevice, s) ||
       hipMemcpyAsync(P->source, source, G * nc0 * sizeof(double), hipMemcpyDeviceToDevice, s))
     return bail(fail(CTF_EHIP, "copy of materials failed"));
-  for (int l = 1; l < P->L; ++l)
+  for (int l = 1; l < P->L; ++l) {
     if (launch_harmonic_coarsen(P->sigt_d[l - 1], P->sigt_d[l], G, P->dims[l].n, s))
       return bail(fail(CTF_EHIP, "harmonic coarsening failed"));
+    if (cfg->coupled_scatter && launch_harmonic_coarsen(P->sigs_d[l - 1], P->sigs_d[l], nl * G * G, P->dims[l].n, s))
+      return bail(fail(CTF_EHIP, "harmonic coarsening failed"));
+  }
   if (P->mixed()) {
     for (int l = 0; l < P->L; ++l)
       if (launch_convert_d2f(P->sigt_d[l], P->sigt_f[l], G * size_t(P->dims[l].n) * P->dims[l].n, s))
         return bail(fail(CTF_EHIP, "conversion failed"));
     if (launch_convert_d2f(P->sigma_s, P->sigma_s_f, nl * size_t(G) * G * nc0, s))
       return bail(fail(CTF_EHIP, "conversion failed"));
+    for (int l = 1; l < P->L && cfg->coupled_scatter; ++l)
+      if (launch_convert_d2f(P->sigs_d[l], P->sigs_f[l], nl * size_t(G) * G * P->dims[l].n * P->dims[l].n, s))
+        return bail(fail(CTF_EHIP, "conversion failed"));
   }
   if (launch_set_int(P->active, 1, s)) return bail(fail(CTF_EHIP, "flag init failed"));
   if (cfg->cnn_level >= 0) {

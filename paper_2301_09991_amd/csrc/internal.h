@@ -81,10 +81,11 @@ hipError_t launch_moments_mfma(const LevelData<float>& L, const float* psi, floa
                                hipStream_t s);
 
 // E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2 (E1, E2 only if nl == 2), divided by 4 pi;
-// source == null: no external source.
+// source == null: no external source.  phi_coarse: phi is on the grid of half the size and read at
+// each cell's parent (the moments of an UpSamp'd correction).
 template <typename T>
 hipError_t launch_emission(const LevelDims& d, const T* phi, const T* sigma_s, int nl,
-                           const T* source, T* E, hipStream_t s);
+                           const T* source, T* E, hipStream_t s, int phi_coarse = 0);
 
 // Finest ConvFEM Petrov-Galerkin operator.
 //   mode 0: out = sign * rho (out and / or out_f; partial: per-block sum of w_n h^2 out^2)
@@ -134,10 +135,12 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 // Correction sweep e_new = e + (rhs - A_up e - sigma_t e) / d on one level.
 //   xmode 0: e from x_in;  1: e = UpSamp(x_coarse) (x_in is the level+1 array, ndc its n_dir);
 //   2: e = 0.   psi_acc != null: psi_acc += e_new instead of writing x_out.
+//   E != null: the emission of the sweep's input e (no external source) is added to rhs, the
+//   scattering-coupled sweep.
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
                                     int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
-                                    int block = 256);
+                                    int block = 256, const T* E = nullptr, int nmomE = 1);
 
 template <typename T>
 hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine,

@@ -201,23 +201,32 @@ __global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, con
 
 // emission E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2, all divided by 4 pi
 template <typename T>
+// phi_coarse: phi is given on the grid of half the size (the moments of UpSamp(e) are those of e
+// on its own level, copied to the 2 x 2 children), read at the parent cell.
 __global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __restrict__ phi,
                                                       const T* __restrict__ ss, int nl,
-                                                      const T* __restrict__ src, T* __restrict__ E) {
+                                                      const T* __restrict__ src, T* __restrict__ E,
+                                                      int phi_coarse) {
   if (idle(d.active)) return;
   const size_t ncell = size_t(d.n) * d.n;
   const size_t t = size_t(blockIdx.x) * kBlock + threadIdx.x;
   const int g = blockIdx.y, G = d.G;
   if (t >= ncell) return;
+  size_t tp = t, np = ncell;
+  if (phi_coarse) {
+    const int j = int(t / d.n), i = int(t % d.n), nh = d.n >> 1;
+    tp = size_t(j >> 1) * nh + (i >> 1);
+    np = size_t(nh) * nh;
+  }
   const int nmom = nl > 1 ? 3 : 1;
   T e0 = src ? src[size_t(g) * ncell + t] : T(0), e1 = 0, e2 = 0;
   for (int gp = 0; gp < G; ++gp) {
     const T s0 = ss[(size_t(g) * G + gp) * ncell + t];
-    e0 += s0 * phi[(size_t(gp) * nmom) * ncell + t];
+    e0 += s0 * phi[(size_t(gp) * nmom) * np + tp];
     if (nl > 1) {
       const T s1 = ss[((size_t(G) + g) * G + gp) * ncell + t];
-      e1 += s1 * phi[(size_t(gp) * nmom + 1) * ncell + t];
-      e2 += s1 * phi[(size_t(gp) * nmom + 2) * ncell + t];
+      e1 += s1 * phi[(size_t(gp) * nmom + 1) * np + tp];
+      e2 += s1 * phi[(size_t(gp) * nmom + 2) * np + tp];
     }
   }
   const T inv4pi = T(0.07957747154594767);  // 1 / (4 pi)
@@ -836,11 +845,12 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
 // it read one row before (every e value is loaded once for the centre and once, from cache, as an
 // x neighbour).  With acc the new value is added to acc instead of being written to xout.
 constexpr int kCorrRows = 8;
-template <typename T, int XMODE>
+template <typename T, int XMODE, bool SCAT>
 __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
                                                          const T* __restrict__ xin, int ndc,
                                                          const T* __restrict__ rhs,
-                                                         T* __restrict__ xout, T* __restrict__ acc) {
+                                                         T* __restrict__ xout, T* __restrict__ acc,
+                                                         const T* __restrict__ E, int nmomE) {
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const int ntx = (n + 63) >> 6;
@@ -876,7 +886,9 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
   const bool prev_in = ju0 >= 0 && ju0 < n;
   // every load of the thread's rows first (rows past the strip end clamped to its last row, so
   // all loads are in bounds and independent), then the sweep itself
-  T ec[kCorrRows], ex[kCorrRows], rh[kCorrRows], sg[kCorrRows], av[kCorrRows];
+  T ec[kCorrRows], ex[kCorrRows], rh[kCorrRows], sg[kCorrRows], av[kCorrRows], q[kCorrRows];
+  // SCAT: the scattering of the correction, E[g][m][cell] (emission of e, no source), as a source
+  const T* __restrict__ Eg = SCAT ? E + size_t(g) * nmomE * ncell : nullptr;
 #pragma unroll
   for (int t = 0; t < kCorrRows; ++t) {
     const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
@@ -886,6 +898,11 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
     rh[t] = rhs[plane + cell];
     sg[t] = sigma[cell];
     av[t] = acc ? acc[plane + cell] : T(0);
+    if (SCAT) {
+      T qv = Eg[cell];
+      if (nmomE > 1) qv += mu * Eg[ncell + cell] + nu * Eg[2 * ncell + cell];
+      q[t] = qv;
+    }
   }
   T eprev = value(clampi(ju0, 0, n - 1), i);   // used only if that row is inside the domain
   const int rows = je - jb;
@@ -898,7 +915,7 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
     const T x = xin_dom ? ex[t] : (xvac ? T(0) : c);
     const T y = (t > 0 || prev_in) ? eprev : (yvac ? T(0) : c);
     const T sig = sg[t];
-    const T r = rh[t] - amu * (c - x) - anu * (c - y) - sig * c;
+    const T r = (SCAT ? rh[t] + q[t] : rh[t]) - amu * (c - x) - anu * (c - y) - sig * c;
     const T enew = c + r / (amu + anu + sig);
     if (acc) acc[plane + cell] = av[t] + enew;
     else xout[plane + cell] = enew;
@@ -1090,10 +1107,10 @@ hipError_t launch_moments_mfma(const LevelData<float>& L, const float* psi, floa
 
 template <typename T>
 hipError_t launch_emission(const LevelDims& d, const T* phi, const T* ss, int nl, const T* src,
-                           T* E, hipStream_t s) {
+                           T* E, hipStream_t s, int phi_coarse) {
   const size_t ncell = size_t(d.n) * d.n;
   hipLaunchKernelGGL(k_emission<T>, dim3(nblocks(ncell), d.G), dim3(kBlock), 0, s, d, phi, ss, nl,
-                     src, E);
+                     src, E, phi_coarse);
   return hipGetLastError();
 }
 
@@ -1205,18 +1222,25 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
 
 template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
-                                    int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
+                                    int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block,
+                                    const T* E, int nmomE) {
   if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
   const int n = L.dims.n;
   const int rows_per_block = (block / 64) * kCorrRows;
   const unsigned nb = unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block);
   const dim3 grid(nb, L.dims.nd, L.dims.G), blk(block);
-  if (xmode == 0)
-    hipLaunchKernelGGL((k_upwind_corr<T, 0>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
-  else if (xmode == 1)
-    hipLaunchKernelGGL((k_upwind_corr<T, 1>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
-  else
-    hipLaunchKernelGGL((k_upwind_corr<T, 2>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, x_out, psi_acc);
+#define CTF_CORR(X, S) hipLaunchKernelGGL((k_upwind_corr<T, X, S>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, \
+                                          x_out, psi_acc, E, nmomE)
+  if (E) {
+    if (xmode == 0) CTF_CORR(0, true);
+    else if (xmode == 1) CTF_CORR(1, true);
+    else CTF_CORR(2, true);
+  } else {
+    if (xmode == 0) CTF_CORR(0, false);
+    else if (xmode == 1) CTF_CORR(1, false);
+    else CTF_CORR(2, false);
+  }
+#undef CTF_CORR
   return hipGetLastError();
 }
 
@@ -1302,7 +1326,7 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
 #define CTF_INSTANTIATE(T)                                                                          \
   template hipError_t launch_moments<T>(const LevelData<T>&, const T*, T*, int, hipStream_t);       \
   template hipError_t launch_emission<T>(const LevelDims&, const T*, const T*, int, const T*, T*,   \
-                                         hipStream_t);                                              \
+                                         hipStream_t, int);                                         \
   template hipError_t launch_pg<T>(int, const LevelData<T>&, const Stencils<T>&, const PGParams&,   \
                                    const PGLaunch<T>&, hipStream_t);                                \
   template hipError_t launch_pg_diffusivity<T>(int, const LevelData<T>&, const Stencils<T>&,        \
@@ -1310,7 +1334,7 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
   template hipError_t launch_upwind_full<T>(const LevelData<T>&, int, const T*, const T*, int, T*,  \
                                             int, T, const T*, hipStream_t);                         \
   template hipError_t launch_upwind_correction<T>(const LevelData<T>&, int, const T*, int, int,     \
-                                                  const T*, T*, T*, hipStream_t, int);              \
+                                                  const T*, T*, T*, hipStream_t, int, const T*, int); \
   template hipError_t launch_restrict<T>(const LevelData<T>&, const LevelData<T>&, const T*, T*,    \
                                          hipStream_t);                                              \
   template hipError_t launch_prolong<T>(const LevelData<T>&, int, const T*, T*, hipStream_t);       \

@@ -29,7 +29,7 @@ EXPORTED = [
     "ctf_solve_batch", "ctf_set_launch_shape", "ctf_get_launch_shape", "ctf_autotune",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
-                 "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32"]
+                 "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32", "corr_scatter"]
 
 
 class Config(ctypes.Structure):
@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
         ("n_pg", ctypes.c_int), ("max_levels", ctypes.c_int), ("beta_pg", ctypes.c_double),
         ("alpha_r", ctypes.c_double), ("eps_k", ctypes.c_double), ("n_inner", ctypes.c_int),
         ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double), ("cnn_max_uses", ctypes.c_int),
-        ("hemisphere", ctypes.c_int),
+        ("hemisphere", ctypes.c_int), ("coupled_scatter", ctypes.c_int),
     ]
 
 
