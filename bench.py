@@ -155,11 +155,15 @@ def time_to_tolerance(log):
     # the last two rows solve the same problem on the xi > 0 half of the ordinates (doubled weights;
     # the 2D flux is even in xi): a separate optimisation, reported beside the others and not part
     # of any DOF count
-    for name, prec, use, half in (("plain_fp64", ctf.FP64, False, False), ("mixed", ctf.FP32_IR, False, False),
-                                  ("learned_mixed", ctf.FP32_IR, True, False),
-                                  ("plain_fp64_half_set", ctf.FP64, False, True),
-                                  ("learned_mixed_half_set", ctf.FP32_IR, True, True)):
-        prob = learned.make_problem(w, inputs, level, precision=prec, hemisphere=half)
+    # "coupled" rows: correction sweeps that include the scattering of the correction (an
+    # extension), also reported beside the others
+    for name, prec, use, half, coupled in (
+            ("plain_fp64", ctf.FP64, False, False, False), ("mixed", ctf.FP32_IR, False, False, False),
+            ("learned_mixed", ctf.FP32_IR, True, False, False),
+            ("plain_fp64_half_set", ctf.FP64, False, True, False),
+            ("learned_mixed_half_set", ctf.FP32_IR, True, True, False),
+            ("coupled_fp64", ctf.FP64, False, False, True), ("coupled_mixed", ctf.FP32_IR, False, False, True)):
+        prob = learned.make_problem(w, inputs, level, precision=prec, hemisphere=half, coupled=coupled)
         if use:
             prob.cnn_attach(theta)
         psi = prob.zeros()

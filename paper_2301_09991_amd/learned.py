@@ -30,12 +30,13 @@ def init_params(seed, device="cuda"):
 
 
 def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=2, max_growth=1.0,
-                 max_uses=2, hemisphere=False):
+                 max_uses=2, hemisphere=False, coupled=False):
     st, ss, src = inputs
     cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
                              scatter_order=ss.shape[0] - 1, discretisation=disc,
                              precision=precision, n_inner=n_inner, cnn_level=cnn_level,
-                             cnn_max_growth=max_growth, cnn_max_uses=max_uses, hemisphere=int(hemisphere))
+                             cnn_max_growth=max_growth, cnn_max_uses=max_uses, hemisphere=int(hemisphere),
+                             coupled_scatter=int(coupled))
     return ctf.Problem(cfg, st, ss, src)
 
 
