@@ -20,7 +20,7 @@ Readings adopted where the paper is silent:
 import numpy as np
 
 from . import quadrature as qd
-from .transport import (VACUUM, emission, pg_diffusivity, pg_residual, source_norm,
+from .transport import (VACUUM, emission, pg_diffusivity, pg_diffusivity_isotropic, pg_residual, source_norm,
                         upwind_advection, upwind_diagonal, upwind_residual, weighted_norm)
 
 UPWIND = "upwind"
@@ -48,7 +48,8 @@ class Problem:
     """A fixed-source problem on the square [0, L]^2 with N x N nodes (h = L / N)."""
 
     def __init__(self, N, L, p, na, sigma_t, sigma_s, source, bc=(VACUUM,) * 4, disc=PG,
-                 n_jacobi=2, n_pg=None, max_levels=0, beta_pg=3.0, quad=None, coupled=False):
+                 n_jacobi=2, n_pg=None, max_levels=0, beta_pg=3.0, quad=None, coupled=False,
+                 isotropic=False):
         self.N, self.L, self.p, self.na = N, L, p, na
         self.h = L / N
         self.sigma_t = np.asarray(sigma_t, dtype=float)
@@ -63,6 +64,7 @@ class Problem:
         # extension (the paper is silent): correction sweeps that include the scattering of the
         # correction on every level
         self.coupled = coupled
+        self.isotropic = isotropic   # the isotropic PG diffusivity instead of the anisotropic one
         q0 = quad if quad is not None else qd.quadrature(na)
         self.levels = [Level(N, self.h, q0, self.sigma_t, self.sigma_s)]
         while True:
@@ -82,7 +84,8 @@ class Problem:
 
     def freeze_k(self, psi):
         """Hold k_x, k_y of psi for the PG_FROZEN discretisation."""
-        self.k_frozen = pg_diffusivity(psi, self.quad, self.h, self.h, self.p, self.bc)
+        fn = pg_diffusivity_isotropic if self.isotropic else pg_diffusivity
+        self.k_frozen = fn(psi, self.quad, self.h, self.h, self.p, self.bc)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -96,7 +99,7 @@ def finest_residual(prob, psi, source=None):
     k = prob.k_frozen if prob.disc == PG_FROZEN else None
     if prob.disc == PG_FROZEN and k is None:
         raise ValueError("PG_FROZEN needs freeze_k first")
-    return pg_residual(psi, q, prob.sigma_t, prob.quad, h, h, prob.p, prob.bc, k=k)
+    return pg_residual(psi, q, prob.sigma_t, prob.quad, h, h, prob.p, prob.bc, k=k, isotropic=prob.isotropic)
 
 
 def apply_operator(prob, psi):

@@ -161,6 +161,35 @@ def pg_diffusivity(psi, quad, dx, dy, p, bc, alpha_r=ALPHA_R, eps_k=EPS_K):
     return kx, ky
 
 
+def pg_diffusivity_isotropic(psi, quad, dx, dy, p, bc, beta_r=ALPHA_R, eps_k=EPS_K):
+    """Isotropic non-linear PG diffusivity, the paper's first residual-based form with the
+    mixed-mass residual estimate (section "Non-Linear Petrov-Galerkin Dissipation"):
+
+        R = beta_r f(mu Psi_x + nu Psi_y; m_L^-1 m - I)
+        k_abs = akabs |R| h / (eps + (|Psi_x| + |Psi_y|) / D),                        D = 2
+        q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
+        k_square = aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|) / D (Psi_x^2 + Psi_y^2))
+        k_max = sqrt((dx mu)^2 + (dy nu)^2),   k = min(k_max, k_abs, k_square),   h = (dx + dy) / 2
+
+    on the interior; the same k acts in x and y: returns (k, k).  beta_r reads as alpha_r = 3."""
+    F = filters_2d(p, dx, dy)
+    Px, Py, _ = pg_gradients(psi, quad, dx, dy, p, bc)
+    mu = quad["mu"][None, :, None, None]
+    nu = quad["nu"][None, :, None, None]
+    Px_i = Px[..., p:-p, p:-p]
+    Py_i = Py[..., p:-p, p:-p]
+    adv = mu * Px + nu * Py
+    R = beta_r * (apply_filter(adv, F["wm"]) - adv[..., p:-p, p:-p])
+    h = 0.5 * (dx + dy)
+    akabs, aksq = alpha_kabs(p), alpha_ksquare(p)
+    k_abs = akabs * np.abs(R) * h / (eps_k + (np.abs(Px_i) + np.abs(Py_i)) / 2.0)
+    q = (mu * Px_i + nu * Py_i) / (eps_k + Px_i**2 + Py_i**2)
+    k_sq = aksq * R**2 * h / (eps_k + (np.abs(q * Px_i) + np.abs(q * Py_i)) / 2.0 * (Px_i**2 + Py_i**2))
+    k_max = np.sqrt((dx * mu) ** 2 + (dy * nu) ** 2) + 0 * k_abs
+    k = np.minimum(np.minimum(k_max, k_abs), k_sq)
+    return k, k
+
+
 def k_diff(psi_ext_p, k, w, p):
     """f^{k-Diff}(Psi; k, w) = f(k.Psi; w) + k.f(Psi; w) - Psi.f(k; w) (eqs. kxx, kyy), taken as
     the definition (the 1/2 of the analytic identity is not in it).  psi_ext_p has a p-wide halo;
@@ -170,15 +199,16 @@ def k_diff(psi_ext_p, k, w, p):
     return apply_filter(k_ext * psi_ext_p, w) + k * apply_filter(psi_ext_p, w) - psi_i * apply_filter(k_ext, w)
 
 
-def pg_residual(psi, q, sigma_t, quad, dx, dy, p, bc, k=None):
+def pg_residual(psi, q, sigma_t, quad, dx, dy, p, bc, k=None, isotropic=False):
     """rho = q - mu Psi_x - nu Psi_y - kDiff_x - kDiff_y - sigma_t psi (lumped mass, w_ml = 1 in
     the per-unit-volume normalisation of the printed filters).
 
-    k = None: non-linear PG, k from psi.  k = (kx, ky): frozen diffusivities.
+    k = None: non-linear PG, k from psi (anisotropic, eq. ano-k; or the isotropic form).
+    k = (kx, ky): frozen diffusivities.
     """
     F = filters_2d(p, dx, dy)
     if k is None:
-        k = pg_diffusivity(psi, quad, dx, dy, p, bc)
+        k = (pg_diffusivity_isotropic if isotropic else pg_diffusivity)(psi, quad, dx, dy, p, bc)
     kx, ky = k
     Px, Py, ext = pg_gradients(psi, quad, dx, dy, p, bc)
     mu = quad["mu"][None, :, None, None]

@@ -205,3 +205,45 @@ def test_kdiff_symmetric_form():
             k_o = kext[..., p + v:p + v + n, p + u:p + u + n]
             ref += w[v + p, u + p] * (k + k_o) * (psi_o - psi_c)
     assert np.allclose(kd, ref, atol=1e-12)
+
+
+def test_isotropic_pg_diffusivity_limits():
+    # 0 <= k <= k_max = sqrt((h mu)^2 + (h nu)^2); k = 0 on a linear field; k_x = k_y
+    from oracle.transport import pg_diffusivity_isotropic
+    quad = qd.quadrature(2)
+    N, h = 10, 0.1
+    rng = np.random.default_rng(6)
+    psi = rng.uniform(size=(1, 32, N, N))
+    kx, ky = pg_diffusivity_isotropic(psi, quad, h, h, 2, VAC)
+    kmax = h * np.sqrt(quad["mu"] ** 2 + quad["nu"] ** 2)[None, :, None, None]
+    assert np.array_equal(kx, ky)
+    assert np.all(kx <= kmax + 1e-15) and np.all(kx >= 0)
+    N = 12
+    xc = (np.arange(N) + 0.5) * h
+    lin = np.broadcast_to((1 + 2 * xc)[None, None, None, :], (1, 32, N, N)).copy()
+    kx, _ = pg_diffusivity_isotropic(lin, quad, h, h, 2, ZG)
+    assert np.abs(kx[..., 4:-4, 4:-4]).max() < 1e-12
+
+
+def test_isotropic_pg_diffusivity_cubic_closed_form():
+    """psi = x^3 with the linear (p = 1) filters, where every quantity has a closed form:
+    Psi_x = ((x+h)^3 - (x-h)^3) / 2h = 3x^2 + h^2, Psi_y = 0, and the mass filter m = [1/6, 2/3, 1/6]
+    maps 3x^2 + h^2 to 3x^2 + 2h^2, so R = beta_r mu h^2; k from the three bounds."""
+    from oracle.transport import pg_diffusivity_isotropic
+    quad = qd.quadrature(2)
+    mu, nu = quad["mu"][:, None], quad["nu"][:, None]
+    N, h, eps, beta_r = 12, 0.3, 1e-3, 3.0
+    x = (np.arange(N) + 0.5) * h
+    psi = np.broadcast_to((x ** 3)[None, None, None, :], (1, 32, N, N)).copy()
+    k, _ = pg_diffusivity_isotropic(psi, quad, h, h, 1, ZG)
+    xi = x[2:-2][None, :]
+    Px = 3 * xi ** 2 + h ** 2
+    R = beta_r * mu * h ** 2
+    akabs, aksq = 2.0 / 16.0, 2.0 / 2.0
+    k_abs = akabs * np.abs(R) * h / (eps + Px / 2.0)
+    q = mu * Px / (eps + Px ** 2)
+    k_sq = aksq * R ** 2 * h / (eps + np.abs(q * Px) / 2.0 * Px ** 2)
+    k_max = h * np.sqrt(mu ** 2 + nu ** 2)
+    ref = np.minimum(np.minimum(k_max, k_abs), k_sq)
+    got = k[0, :, 2:-2, 2:-2]
+    assert np.allclose(got, ref[:, None, :], rtol=1e-10, atol=1e-15)
