@@ -87,6 +87,10 @@ typedef struct ctf_config {
                             external source), so the coarse levels correct the scattering modes too;
                             the discrete equations and their solution are unchanged.  An extension
                             (the paper's sweeps are transport-only).  Default 0. */
+  int pg_isotropic;      /* 1: the isotropic non-linear PG diffusivity (section "Non-Linear
+                            Petrov-Galerkin Dissipation": mixed-mass residual R, k = min(k_max, k_abs,
+                            k_square), the same k in x and y) instead of the anisotropic pair of
+                            eq. ano-k.  Default 0. */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;

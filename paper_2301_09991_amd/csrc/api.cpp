@@ -59,6 +59,7 @@ int validate(const ctf_config* c) {
     return fail(CTF_EUNSUPPORTED, "the learned correction supports one energy group");
   if (c->hemisphere != 0 && c->hemisphere != 1) return fail(CTF_EINVAL, "hemisphere 0 or 1");
   if (c->coupled_scatter != 0 && c->coupled_scatter != 1) return fail(CTF_EINVAL, "coupled_scatter 0 or 1");
+  if (c->pg_isotropic != 0 && c->pg_isotropic != 1) return fail(CTF_EINVAL, "pg_isotropic 0 or 1");
   return CTF_OK;
 }
 
@@ -741,6 +742,7 @@ void ctf_default_config(ctf_config* c) {
   c->cnn_max_uses = 2;
   c->hemisphere = 0;
   c->coupled_scatter = 0;
+  c->pg_isotropic = 0;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -796,6 +798,7 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   P->pp.alpha_ksq = std::pow(2.0, p) / 2.0;
   P->pp.beta = cfg->beta_pg;
   P->pp.bc_vac = P->bc_vac;
+  P->pp.isotropic = cfg->pg_isotropic;
 
   hipStream_t s = P->stream;
   auto bail = [&](int code) {

@@ -69,6 +69,7 @@ struct LevelData {
 struct PGParams {
   double alpha_r, eps_k, alpha_kabs, alpha_ksq, beta;
   int bc_vac;
+  int isotropic = 0;   // 1: the isotropic diffusivity (k_x = k_y) instead of the anisotropic pair
 };
 
 // ---- kernel launchers (kernels.hip) ------------------------------------------------------------

@@ -45,6 +45,20 @@ __device__ __forceinline__ T pg_k(T mu, T R, T Psi, T h, T akabs, T aksq, T eps)
               qdiv(aksq * R * R * h, eps + tabs(mu) * Psi * Psi));
 }
 
+// Isotropic diffusivity (the residual-based form with the mixed-mass residual R = R_x + R_y):
+//   k = min(sqrt((h mu)^2 + (h nu)^2), akabs |R| h / (eps + (|Psi_x| + |Psi_y|)/2),
+//           aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|)/2 (Psi_x^2 + Psi_y^2))),
+//   q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
+template <typename T>
+__device__ __forceinline__ T pg_k_iso(T mu, T nu, T R, T px, T py, T h, T akabs, T aksq, T eps) {
+  const T s2 = px * px + py * py;
+  const T q = qdiv(mu * px + nu * py, eps + s2);
+  const T kabs = qdiv(akabs * tabs(R) * h, eps + (tabs(px) + tabs(py)) * T(0.5));
+  const T ksq = qdiv(aksq * R * R * h, eps + (tabs(q * px) + tabs(q * py)) * T(0.5) * s2);
+  const T hm = h * mu, hn = h * nu;
+  return tmin(tmin(T(sqrt(hm * hm + hn * hn)), kabs), ksq);
+}
+
 __device__ __forceinline__ int parent_dir_dev(int n, int na) {
   if (na == 1) return n;
   const int na2 = na * na;
@@ -263,6 +277,7 @@ struct PGArgs {
   double* partial;    // optional per-block sum of w_n h^2 out^2 (mode 0)
   float* kx_out_f;    // optional float copies of the computed diffusivities
   float* ky_out_f;
+  int iso;            // isotropic diffusivity
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -560,8 +575,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
         const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
         const T rx = ar * mu * (yrot(wMx, cm, t) - px);
         const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-        const T kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
-        const T ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+        T kx, ky;
+        if (a.iso) {
+          kx = ky = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+        } else {
+          kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
+          ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+        }
         const size_t ro = base + size_t(o) * n;
         if (a.kx_out) {
           at(a.kx_out + ro, bo) = kx;
@@ -721,8 +741,14 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
           const T ry = ar * nu * (yrot(wMy, cm, t) - py);
           T* const k0r = &s_k[sk][0][P];
           T* const k1r = &s_k[sk][1][P];
-          k0r[lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
-          k1r[lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          if (a.iso) {
+            const T kk = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+            k0r[lane] = kk;
+            k1r[lane] = kk;
+          } else {
+            k0r[lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
+            k1r[lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          }
           if (edge_strip) {
             // columns outside the domain take k of the nearest interior column
             __syncthreads();
@@ -1125,6 +1151,7 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
   a.aksq = T(pp.alpha_ksq);
   a.beta = T(pp.beta);
   a.bc_vac = pp.bc_vac;
+  a.iso = pp.isotropic;
   a.psi = o.psi;
   a.E = o.E;
   a.nmomE = o.nmomE;

@@ -40,7 +40,7 @@ class Config(ctypes.Structure):
         ("n_pg", ctypes.c_int), ("max_levels", ctypes.c_int), ("beta_pg", ctypes.c_double),
         ("alpha_r", ctypes.c_double), ("eps_k", ctypes.c_double), ("n_inner", ctypes.c_int),
         ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double), ("cnn_max_uses", ctypes.c_int),
-        ("hemisphere", ctypes.c_int), ("coupled_scatter", ctypes.c_int),
+        ("hemisphere", ctypes.c_int), ("coupled_scatter", ctypes.c_int), ("pg_isotropic", ctypes.c_int),
     ]
 
 
