@@ -182,6 +182,65 @@ def time_to_tolerance(log):
     return out
 
 
+def duct_study(log):
+    """The paper's straight-duct study (28 x 36 cm, void duct, no scattering) as a self-convergence
+    study: upwind discretisation (the non-linear PG iteration does not converge with the void
+    duct), 128 ordinates at dx = 0.8, 0.4, 0.2, 0.1 cm and 512 at dx = 0.1; relative L2 errors of
+    the scalar flux over the 28 x 36 cm domain against the dx = 0.1 solution averaged onto each
+    grid (spatial, 128 ordinates) and between 128 and 512 ordinates at dx = 0.1 (angular); the
+    flux along the duct centre line x = 14 cm; and the PG residual after the paper's 100 cycles at
+    dx = 0.4 for p = 1, 2, 3."""
+    import numpy as np
+    import torch
+    from paper_2301_09991_amd import ctf
+    from workloads import DUCT_PAD, duct_inputs
+
+    def run(dx, na, disc=ctf.UPWIND, p=1, rtol=1e-10, cycles=3000):
+        N, L, st, ss, src = duct_inputs(dx)
+        cfg = ctf.default_config(n=N, length=L, p=p, na=na, ngroups=1, scatter_order=0, discretisation=disc)
+        prob = ctf.Problem(cfg, st, ss, src)
+        psi = prob.zeros()
+        info = prob.solve(psi, rtol, cycles)
+        phi = torch.empty((1, 3, N, N), dtype=torch.float64, device="cuda")
+        prob.moments(psi, phi)
+        return info, phi[0, 0].cpu().numpy()
+
+    out = {"solves": {}}
+    flux = {}
+    for dx, na in ((0.8, 4), (0.4, 4), (0.2, 4), (0.1, 4), (0.1, 8)):
+        info, phi = run(dx, na)
+        flux[(dx, na)] = phi
+        out["solves"][f"dx{dx}_na{na}"] = {"cycles": info["cycles"], "converged": info["converged"],
+                                           "seconds": info["seconds"]}
+        log(f"duct dx={dx} na={na}: {info['cycles']} cycles, {info['seconds']:.3f} s")
+    def rel_err(dx, na, ref):
+        f = int(round(dx / 0.1))
+        n = ref.shape[0] // f
+        refc = ref.reshape(n, f, n, f).mean(axis=(1, 3))
+        pad = int(round(DUCT_PAD / dx))
+        d = (flux[(dx, na)] - refc)[:, pad:n - pad]
+        return float(np.sqrt((d ** 2).sum() / (refc[:, pad:n - pad] ** 2).sum()))
+
+    # spatial: 128-ordinate solutions against the 128-ordinate dx = 0.1 one; angular: 128 against
+    # 512 ordinates at dx = 0.1
+    errs = {f"dx{dx}": rel_err(dx, 4, flux[(0.1, 4)]) for dx in (0.8, 0.4, 0.2)}
+    out["spatial_rel_l2_error_vs_dx0.1"] = errs
+    out["angular_rel_l2_error_128_vs_512_at_dx0.1"] = rel_err(0.1, 4, flux[(0.1, 8)])
+    e = [errs[f"dx{dx}"] for dx in (0.8, 0.4, 0.2)]
+    out["observed_order"] = [float(np.log2(e[0] / e[1])), float(np.log2(e[1] / e[2]))]
+    # the flux along the duct centre line (x = 14 cm in the 28 cm frame) at dx = 0.2, every 1 cm
+    phi = flux[(0.2, 4)]
+    col = int(round((14.0 + DUCT_PAD) / 0.2))
+    out["centre_line_phi_dx0.2"] = [float(0.5 * (phi[j, col - 1] + phi[j, col])) for j in range(2, 180, 5)]
+    pg = {}
+    for p in (1, 2, 3):
+        info, _ = run(0.4, 4, ctf.CONVFEM_PG, p, rtol=1e-10, cycles=100)
+        pg[f"p{p}"] = {"cycles": info["cycles"], "rel_residual": info["rel_residual"]}
+    out["pg_after_100_cycles_dx0.4"] = pg
+    log(f"duct errors {errs}, orders {out['observed_order']}")
+    return out
+
+
 def batched(log):
     """The batched workload: 64 problems with sizes drawn from {64, ..., 384}^2, p = 2, 512
     ordinates, one group, upwind discretisation, float32 cycles + float64 refinement to 1e-6, all
@@ -225,6 +284,8 @@ def main():
     ap.add_argument("--workload", default="c1_mixed")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the time-to-tolerance and batched measurements")
+    ap.add_argument("--duct-study", action="store_true",
+                    help="also run the straight-duct self-convergence study (reported in the JSON line)")
     ap.add_argument("--launch-shape", default=None,
                     help="strip_h,corr_block,pg_fused for the timed problem (default: the library's)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -338,6 +399,8 @@ def main():
         line["time_to_tol"] = time_to_tolerance(log)
         torch.cuda.empty_cache()
         line["batched"] = batched(log)
+    if args.duct_study:
+        line["duct_study"] = duct_study(log)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline()

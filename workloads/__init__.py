@@ -127,3 +127,39 @@ def random_field(shape, seed, lo=-1.0, hi=1.0):
     """Seeded uniform random array (test vectors such as psi for operator parity)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(lo, hi, size=shape)
+
+
+# ------------------------------------------------------------------------------------------------
+# Straight-duct problem (the paper's mono-energetic fixed-source duct study; its table of
+# regions): a 28 cm (x) by 36 cm (y) domain.  Region 1, the 6 x 6 cm source in the centre
+# (x in [11, 17], y in [15, 21]): S = 1, sigma_a = 0.5; region 2, absorber on both sides of the
+# duct column (x < 11 or x > 17): sigma_a = 0.5; region 3, the duct above and below the source
+# (x in [11, 17]): void.  No scattering.  The solver's domains are square, so the 28 cm width is
+# centred in a 36 cm square and the 4 cm on either side are void: with no scattering there, a
+# particle that leaves the 28 cm domain never returns, as at a vacuum boundary.  Each cell takes
+# the area average of sigma and S over it, so that every resolution (the region edges fall inside
+# cells at dx = 0.8 and 0.4) carries the same total source and absorber.
+DUCT_WIDTH, DUCT_HEIGHT = 28.0, 36.0
+DUCT_PAD = (DUCT_HEIGHT - DUCT_WIDTH) / 2.0
+
+
+def _overlap(a0, a1, b0, b1):
+    return np.clip(np.minimum(a1, b1) - np.maximum(a0, b0), 0.0, None)
+
+
+def duct_inputs(dx):
+    """(N, L, sigma_t[1, N, N], sigma_s[1, 1, 1, N, N], source[1, N, N]) at node spacing dx."""
+    L = DUCT_HEIGHT
+    N = int(round(L / dx))
+    if abs(N * dx - L) > 1e-9 * L:
+        raise ValueError("dx must divide 36 cm")
+    e0 = np.arange(N) * dx
+    x0, x1 = e0 - DUCT_PAD, e0 + dx - DUCT_PAD    # cell edges in the 28 cm frame
+    y0, y1 = e0, e0 + dx
+    fx_abs = (_overlap(x0, x1, 0.0, 11.0) + _overlap(x0, x1, 17.0, DUCT_WIDTH)) / dx
+    fx_col = _overlap(x0, x1, 11.0, 17.0) / dx
+    fy_src = _overlap(y0, y1, 15.0, 21.0) / dx
+    f_src = fy_src[:, None] * fx_col[None, :]
+    f_abs = np.ones((N, 1)) * fx_abs[None, :]
+    sigma = 0.5 * (f_abs + f_src)
+    return N, L, sigma[None].copy(), np.zeros((1, 1, 1, N, N)), f_src[None].copy()
