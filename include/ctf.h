@@ -59,7 +59,7 @@ enum { CTF_SMOOTH_UPWIND = 0, CTF_SMOOTH_FINEST = 1 };
 typedef struct ctf_config {
   int n;               /* nodes per side of the finest grid (N x N), N >= 2 */
   double length;       /* side L of the square domain; h = L / N */
-  int p;               /* ConvFEM degree 1..3 (ignored by CTF_UPWIND) */
+  int p;               /* ConvFEM degree 1..4 (ignored by CTF_UPWIND) */
   int na;              /* ordinates per face side, a power of two: n_dir = 8 na^2 */
   int ngroups;         /* G >= 1 */
   int scatter_order;   /* 0 isotropic, 1 adds linearly anisotropic (P1) scattering */

@@ -40,7 +40,7 @@ int validate(const ctf_config* c) {
   if (c->n < 2) return fail(CTF_EINVAL, "n must be >= 2");
   if (!(c->length > 0.0)) return fail(CTF_EINVAL, "length must be > 0");
   if (c->discretisation != CTF_UPWIND && (c->p < 1 || c->p > kMaxP))
-    return fail(CTF_EINVAL, "p must be 1..3");
+    return fail(CTF_EINVAL, "p must be 1..4");
   if (!is_pow2(c->na)) return fail(CTF_EINVAL, "na must be a power of two");
   if (c->ngroups < 1) return fail(CTF_EINVAL, "ngroups must be >= 1");
   if (c->scatter_order < 0 || c->scatter_order > 1) return fail(CTF_EINVAL, "scatter_order 0 or 1");
@@ -898,7 +898,7 @@ int ctf_level_quadrature(const ctf_problem* P, int level, double* mu, double* nu
 }
 
 int ctf_convfem_stencils(int p, double* m, double* d, double* k) {
-  if (p < 1 || p > kMaxP) return fail(CTF_EINVAL, "p must be 1..3");
+  if (p < 1 || p > kMaxP) return fail(CTF_EINVAL, "p must be 1..4");
   double mm[2 * kMaxP + 1], dd[2 * kMaxP + 1], kk[2 * kMaxP + 1];
   convfem_stencils(p, mm, dd, kk);
   for (int i = 0; i < 2 * p + 1; ++i) {

@@ -13,7 +13,7 @@
 
 namespace ctf {
 
-constexpr int kMaxP = 3;
+constexpr int kMaxP = 4;
 constexpr int kMaxLevels = 16;
 
 // ---- host-side setup (setup.cpp) ---------------------------------------------------------------

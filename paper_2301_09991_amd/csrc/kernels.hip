@@ -1179,6 +1179,7 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
     case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_pg_diffusivity<3, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pg_diffusivity<4, T>), grid, dim3(kStripW), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1202,6 +1203,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
       case 1: hipLaunchKernelGGL((k_pg_fused<1, T>), grid, dim3(kStripW), 0, s, a); break;
       case 2: hipLaunchKernelGGL((k_pg_fused<2, T>), grid, dim3(kStripW), 0, s, a); break;
       case 3: hipLaunchKernelGGL((k_pg_fused<3, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 4: hipLaunchKernelGGL((k_pg_fused<4, T>), grid, dim3(kStripW), 0, s, a); break;
       default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -1226,6 +1228,7 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
     case 1: hipLaunchKernelGGL((k_pg_stream<1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 2: hipLaunchKernelGGL((k_pg_stream<2, T>), grid, dim3(kStripW), 0, s, a); break;
     case 3: hipLaunchKernelGGL((k_pg_stream<3, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_pg_stream<4, T>), grid, dim3(kStripW), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

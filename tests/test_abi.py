@@ -38,7 +38,7 @@ def test_host_quadrature_matches_oracle(na):
     assert np.abs(w - q["p"]).max() < 1e-13
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
 def test_host_stencils_match_oracle(p):
     m, d, k = ctf.convfem_stencils(p)
     mo, do, ko = convfem.stencils_1d_float(p)
@@ -51,7 +51,7 @@ def test_config_validation():
     with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(na=3))
     with pytest.raises(ctf.CtfError):
-        ctf.workspace_bytes(ctf.default_config(p=4))
+        ctf.workspace_bytes(ctf.default_config(p=5))
     with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(n=1))
     with pytest.raises(ctf.CtfError):

@@ -51,7 +51,7 @@ def _blocks(lines):
 
 def test_host_setup_under_sanitizers_matches_oracle(output):
     blocks = _blocks(output)
-    assert len(blocks) == 3 * 2 * 2 + 3
+    assert len(blocks) == 3 * 2 * 2 + 4   # na 1, 2, 4 x full / half x fine / coarse; p = 1..4
     for kind, key, vals in blocks:
         if kind == "Q":
             na, faces, coarse = key

@@ -158,11 +158,14 @@ def _mms_truncation(p, N, quad):
     return weighted_norm(r, quad, h, h)
 
 
-@pytest.mark.parametrize("p,order_lo,order_hi", [(1, 1.85, 2.15), (2, 3.6, 4.4), (3, 3.4, 4.4)])
-def test_manufactured_solution_truncation_order(p, order_lo, order_hi):
+@pytest.mark.parametrize("p,order_lo,order_hi,n", [(1, 1.85, 2.15, 64), (2, 3.6, 4.4, 64), (3, 3.4, 4.4, 64),
+                                                     (4, 5.0, 6.6, 128)])
+def test_manufactured_solution_truncation_order(p, order_lo, order_hi, n):
+    # p = 4 (formal order 6) is pre-asymptotic below N = 128 on this bump: the limiter's
+    # dissipation still acts there (orders 2.6 and 9.1 between 32, 64 and 128)
     quad = qd.quadrature(1)
-    e1 = _mms_truncation(p, 64, quad)
-    e2 = _mms_truncation(p, 128, quad)
+    e1 = _mms_truncation(p, n, quad)
+    e2 = _mms_truncation(p, 2 * n, quad)
     order = np.log2(e1 / e2)
     assert order_lo < order < order_hi, order
 
