@@ -127,6 +127,7 @@ struct ctf_problem {
   double* partial = nullptr;
   double* scal = nullptr;  // device scalars
   int npartial = 0;
+  size_t partial_cap = 0;   // length of partial
   double bnorm = 0.0;
   Stencils<double> st_d{};
   Stencils<float> st_f{};
@@ -254,7 +255,8 @@ size_t layout(ctf_problem* P, char* base) {
     P->cnn_backup = c.take<double>(P->dof(0));
   }
   P->npartial = wnorm2_partials(P->dims[0]);
-  P->partial = c.take<double>(std::max<size_t>(P->npartial, pg_partials(P->dims[0], 8)));
+  P->partial_cap = std::max<size_t>({size_t(P->npartial), pg_partials(P->dims[0], 8), upwind_full_blocks(P->dims[0])});
+  P->partial = c.take<double>(P->partial_cap);
   P->scal = c.take<double>(8);
   P->active = c.take<int>(64);
   for (int l = 0; l < P->L; ++l) P->dims[l].active = P->active;
@@ -321,15 +323,16 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
              float* out_f = nullptr, bool want_norm = false, bool k_float = false) {
   const ctf_config& c = P->cfg;
   if (c.discretisation == CTF_UPWIND) {
-    if (out_f) return fail(CTF_EUNSUPPORTED, "internal: float output of the upwind operator");
+    double* partial = (mode == 0 && want_norm) ? P->partial : nullptr;
+    int np = 0;
     {
       Timed t(P, CTF_T_UPWIND64);
       CTF_HIP(launch_upwind_full<double>(P->ld(0), P->bc_vac, psi, P->E, P->nmom, out, mode, sign,
-                                         nullptr, P->stream));
+                                         nullptr, P->stream, out_f, partial, P->partial_cap, &np));
     }
-    if (want_norm) {
+    if (partial) {
       Timed t(P, CTF_T_NORM);
-      CTF_HIP(launch_wnorm2<double>(P->ld(0), out, P->partial, P->npartial, P->scal, P->stream));
+      CTF_HIP(launch_sum_partials(P->partial, np, P->scal, P->stream, P->active));
     }
     return CTF_OK;
   }
@@ -597,9 +600,8 @@ int outer_residual_async(ctf_problem* P, const double* psi) {
   const int disc = P->cfg.discretisation;
   const size_t n = P->dof(0);
   if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, false);
-  rc = finest64(P, psi, P->rho[0], 0, 1.0, nullptr, true, false);
+  rc = finest64(P, psi, nullptr, 0, 1.0, P->r_f, true, false);
   if (rc) return rc;
-  CTF_HIP(launch_convert_d2f(P->rho[0], P->r_f, n, P->stream, P->active));
   if (disc == CTF_CONVFEM_PG_FROZEN_K) {
     CTF_HIP(launch_convert_d2f(P->kx, P->kx_f, n, P->stream, P->active));
     CTF_HIP(launch_convert_d2f(P->ky, P->ky_f, n, P->stream, P->active));

@@ -128,10 +128,16 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
 // number of per-block partial sums a mode-0 launch_pg writes with this strip height
 size_t pg_partials(const LevelDims& d, int strip_h);
 
-// Finest upwind operator: mode 0 out = sign * rho, mode 1 out = psi + rho / d.
+// Finest upwind operator: mode 0 out = sign * rho (to out and / or out_f; with partial, one float64
+// partial sum of w_n h^2 (sign rho)^2 per block, their count in *npartial, at most partial_cap),
+// mode 1 out = psi + rho / d.
 template <typename T>
 hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, const T* E,
-                              int nmomE, T* out, int mode, T sign, const T* rhs, hipStream_t s);
+                              int nmomE, T* out, int mode, T sign, const T* rhs, hipStream_t s,
+                              float* out_f = nullptr, double* partial = nullptr, size_t partial_cap = 0,
+                              int* npartial = nullptr);
+// number of per-block partial sums a mode-0 launch_upwind_full writes
+size_t upwind_full_blocks(const LevelDims& d);
 
 // Correction sweep e_new = e + (rhs - A_up e - sigma_t e) / d on one level.
 //   xmode 0: e from x_in;  1: e = UpSamp(x_coarse) (x_in is the level+1 array, ndc its n_dir);

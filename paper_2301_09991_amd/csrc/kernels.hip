@@ -832,36 +832,102 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
 
 // ---------------------------------------------------------------------------------------------
 // finest upwind operator (eq. discretised_hfm): rho = q - A_up psi - sigma_t psi
+// mode 0: out = sign * rho (to out and / or out_f), with one float64 partial sum of
+// w_n h^2 (sign rho)^2 per block when partial is given; mode 1: out = psi + rho / d (a Jacobi sweep).
+// Threads are laid out as in the correction sweep below: 64 columns x row groups of kCorrRows rows,
+// each thread walking its rows in the ordinate's downwind y order with every load issued up front
+// from clamped addresses, so psi is read once for the centre and once, from cache, as x neighbour.
+constexpr int kCorrRows = 8;
+constexpr int kFullBlock = 256;
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_vac,
-                                                         const T* __restrict__ psi,
-                                                         const T* __restrict__ E, int nmomE,
-                                                         T* __restrict__ out, int mode, T sign,
-                                                         const T* __restrict__ rhs) {
+__global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int bc_vac,
+                                                            const T* __restrict__ psi,
+                                                            const T* __restrict__ E, int nmomE,
+                                                            T* __restrict__ out, float* __restrict__ out_f,
+                                                            int mode, T sign, const T* __restrict__ rhs,
+                                                            double* __restrict__ partial) {
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
-  const size_t ncell = size_t(n) * n;
-  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
-  if (cell >= int(ncell)) return;
+  const int ntx = (n + 63) >> 6;
+  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
+  const int i = tx * 64 + int(threadIdx.x & 63);
+  const int jb = (ty * (kFullBlock / 64) + int(threadIdx.x >> 6)) * kCorrRows;
   const int dir = blockIdx.y, g = blockIdx.z;
-  const size_t idx = (size_t(g) * nd + dir) * ncell + cell;
-  const int j = cell / n, i = cell - j * n;
-  const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
-  const T pc = psi[idx];
-  T px, py;
-  if (mu > T(0)) px = i > 0 ? psi[idx - 1] : ((bc_vac & 1) ? T(0) : pc);
-  else px = i < n - 1 ? psi[idx + 1] : ((bc_vac & 2) ? T(0) : pc);
-  if (nu > T(0)) py = j > 0 ? psi[idx - n] : ((bc_vac & 4) ? T(0) : pc);
-  else py = j < n - 1 ? psi[idx + n] : ((bc_vac & 8) ? T(0) : pc);
-  const T amu = tabs(mu) / h, anu = tabs(nu) / h;
-  const size_t eb = size_t(g) * nmomE * ncell + cell;
-  T q = E[eb];
-  if (nmomE > 1) q += mu * E[eb + ncell] + nu * E[eb + 2 * ncell];
-  if (rhs) q += rhs[idx];
-  const T sig = L.sigma_t[size_t(g) * ncell + cell];
-  const T rho = q - amu * (pc - px) - anu * (pc - py) - sig * pc;
-  if (mode == 0) out[idx] = sign * rho;
-  else out[idx] = pc + rho / (amu + anu + sig);
+  const size_t ncell = size_t(n) * n;
+  const size_t plane = (size_t(g) * nd + dir) * ncell;
+  double acc = 0.0;
+  if (i < n && jb < n) {
+    const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
+    const int je = min(jb + kCorrRows, n);
+    const int iu = mu > T(0) ? i - 1 : i + 1;
+    const bool x_in = iu >= 0 && iu < n;
+    const int iuc = clampi(iu, 0, n - 1);
+    const bool xvac = mu > T(0) ? (bc_vac & 1) : (bc_vac & 2);
+    const bool yvac = nu > T(0) ? (bc_vac & 4) : (bc_vac & 8);
+    const T amu = tabs(mu) / h, anu = tabs(nu) / h;
+    const T* __restrict__ sg = L.sigma_t + size_t(g) * ncell;
+    const T* __restrict__ pp = psi + plane;
+    const T* __restrict__ E0 = E + size_t(g) * nmomE * ncell;
+    const T* __restrict__ E1 = nmomE > 1 ? E0 + ncell : E0;
+    const T* __restrict__ E2 = nmomE > 1 ? E0 + 2 * ncell : E0;
+    const T* __restrict__ rp = rhs ? rhs + plane : E0;
+    const bool down = nu > T(0);
+    const int j0 = down ? jb : je - 1;
+    const int ju = down ? j0 - 1 : j0 + 1;
+    const bool y_in = ju >= 0 && ju < n;
+    T vc[kCorrRows], vx[kCorrRows], q0[kCorrRows], q1[kCorrRows], q2[kCorrRows], vr[kCorrRows],
+        vs[kCorrRows];
+#pragma unroll
+    for (int t = 0; t < kCorrRows; ++t) {
+      const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
+      const size_t row = size_t(j) * n;
+      vc[t] = pp[row + i];
+      vx[t] = pp[row + iuc];
+      q0[t] = E0[row + i];
+      q1[t] = E1[row + i];
+      q2[t] = E2[row + i];
+      vr[t] = rp[row + i];
+      vs[t] = sg[row + i];
+    }
+    T prev = pp[size_t(clampi(ju, 0, n - 1)) * n + i];   // the upwind row, used only inside the domain
+    const int rows = je - jb;
+#pragma unroll
+    for (int t = 0; t < kCorrRows; ++t) {
+      if (t >= rows) break;
+      const size_t cell = size_t(down ? j0 + t : j0 - t) * n + i;
+      const T pc = vc[t];
+      const T px = x_in ? vx[t] : (xvac ? T(0) : pc);
+      const T py = (t > 0 || y_in) ? prev : (yvac ? T(0) : pc);
+      T q = q0[t];
+      if (nmomE > 1) q += mu * q1[t] + nu * q2[t];
+      if (rhs) q += vr[t];
+      const T sig = vs[t];
+      const T rho = q - amu * (pc - px) - anu * (pc - py) - sig * pc;
+      if (mode == 0) {
+        const T val = sign * rho;
+        if (out) out[plane + cell] = val;
+        if (out_f) out_f[plane + cell] = float(val);
+        acc += double(val) * double(val);
+      } else {
+        out[plane + cell] = pc + rho / (amu + anu + sig);
+      }
+      prev = pc;
+    }
+  }
+  if (partial) {
+    // block sum in a fixed order (deterministic), one partial per block
+    __shared__ double red[kFullBlock];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int st = kFullBlock / 2; st > 0; st >>= 1) {
+      if (int(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
+      partial[b] = red[0] * double(L.w[dir]) * L.dims.h * L.dims.h;
+    }
+  }
 }
 
 // correction sweep on one level: e_new = e + (rhs - A_up e - sigma_t e) / d
@@ -870,7 +936,6 @@ __global__ __launch_bounds__(kBlock) void k_upwind_full(LevelData<T> L, int bc_v
 // rows and walks them in the ordinate's downwind y order, so the upwind y neighbour is the value
 // it read one row before (every e value is loaded once for the centre and once, from cache, as an
 // x neighbour).  With acc the new value is added to acc instead of being written to xout.
-constexpr int kCorrRows = 8;
 template <typename T, int XMODE, bool SCAT>
 __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
                                                          const T* __restrict__ xin, int ndc,
@@ -1241,12 +1306,25 @@ size_t pg_partials(const LevelDims& d, int strip_h) {
   return strips * d.nd * d.G;
 }
 
+size_t upwind_full_blocks(const LevelDims& d) {
+  const int rows_per_block = (kFullBlock / 64) * kCorrRows;
+  return size_t((d.n + 63) / 64) * ((d.n + rows_per_block - 1) / rows_per_block) * d.nd * d.G;
+}
+
 template <typename T>
 hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, const T* E, int nmomE,
-                              T* out, int mode, T sign, const T* rhs, hipStream_t s) {
-  const dim3 grid(nblocks(size_t(L.dims.n) * L.dims.n), L.dims.nd, L.dims.G);
-  hipLaunchKernelGGL(k_upwind_full<T>, grid, dim3(kBlock), 0, s, L, bc_vac, psi, E,
-                     nmomE, out, mode, sign, rhs);
+                              T* out, int mode, T sign, const T* rhs, hipStream_t s, float* out_f,
+                              double* partial, size_t partial_cap, int* npartial) {
+  const int n = L.dims.n;
+  const int rows_per_block = (kFullBlock / 64) * kCorrRows;
+  const dim3 grid(unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block), L.dims.nd,
+                  L.dims.G);
+  const size_t blocks = size_t(grid.x) * grid.y * grid.z;
+  if (partial && blocks > partial_cap) return hipErrorInvalidValue;
+  if (mode == 0 && !out && !out_f) return hipErrorInvalidValue;
+  if (npartial) *npartial = int(blocks);
+  hipLaunchKernelGGL(k_upwind_full<T>, grid, dim3(kFullBlock), 0, s, L, bc_vac, psi, E, nmomE, out, out_f,
+                     mode, sign, rhs, partial);
   return hipGetLastError();
 }
 
@@ -1362,7 +1440,8 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
   template hipError_t launch_pg_diffusivity<T>(int, const LevelData<T>&, const Stencils<T>&,        \
                                                const PGParams&, const PGLaunch<T>&, hipStream_t);   \
   template hipError_t launch_upwind_full<T>(const LevelData<T>&, int, const T*, const T*, int, T*,  \
-                                            int, T, const T*, hipStream_t);                         \
+                                            int, T, const T*, hipStream_t, float*, double*, size_t,  \
+                                            int*);                                                  \
   template hipError_t launch_upwind_correction<T>(const LevelData<T>&, int, const T*, int, int,     \
                                                   const T*, T*, T*, hipStream_t, int, const T*, int); \
   template hipError_t launch_restrict<T>(const LevelData<T>&, const LevelData<T>&, const T*, T*,    \
