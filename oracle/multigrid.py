@@ -49,7 +49,7 @@ class Problem:
 
     def __init__(self, N, L, p, na, sigma_t, sigma_s, source, bc=(VACUUM,) * 4, disc=PG,
                  n_jacobi=2, n_pg=None, max_levels=0, beta_pg=3.0, quad=None, coupled=False,
-                 isotropic=False):
+                 isotropic=False, r_estimate="mixed"):
         self.N, self.L, self.p, self.na = N, L, p, na
         self.h = L / N
         self.sigma_t = np.asarray(sigma_t, dtype=float)
@@ -65,6 +65,7 @@ class Problem:
         # correction on every level
         self.coupled = coupled
         self.isotropic = isotropic   # the isotropic PG diffusivity instead of the anisotropic one
+        self.r_estimate = r_estimate  # its residual estimate: "mixed", "low" or "high"
         q0 = quad if quad is not None else qd.quadrature(na)
         self.levels = [Level(N, self.h, q0, self.sigma_t, self.sigma_s)]
         while True:
@@ -84,8 +85,11 @@ class Problem:
 
     def freeze_k(self, psi):
         """Hold k_x, k_y of psi for the PG_FROZEN discretisation."""
-        fn = pg_diffusivity_isotropic if self.isotropic else pg_diffusivity
-        self.k_frozen = fn(psi, self.quad, self.h, self.h, self.p, self.bc)
+        if self.isotropic:
+            self.k_frozen = pg_diffusivity_isotropic(psi, self.quad, self.h, self.h, self.p, self.bc,
+                                                     r_estimate=self.r_estimate)
+        else:
+            self.k_frozen = pg_diffusivity(psi, self.quad, self.h, self.h, self.p, self.bc)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -99,7 +103,8 @@ def finest_residual(prob, psi, source=None):
     k = prob.k_frozen if prob.disc == PG_FROZEN else None
     if prob.disc == PG_FROZEN and k is None:
         raise ValueError("PG_FROZEN needs freeze_k first")
-    return pg_residual(psi, q, prob.sigma_t, prob.quad, h, h, prob.p, prob.bc, k=k, isotropic=prob.isotropic)
+    return pg_residual(psi, q, prob.sigma_t, prob.quad, h, h, prob.p, prob.bc, k=k, isotropic=prob.isotropic,
+                       r_estimate=prob.r_estimate)
 
 
 def apply_operator(prob, psi):

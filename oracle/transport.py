@@ -161,25 +161,61 @@ def pg_diffusivity(psi, quad, dx, dy, p, bc, alpha_r=ALPHA_R, eps_k=EPS_K):
     return kx, ky
 
 
-def pg_diffusivity_isotropic(psi, quad, dx, dy, p, bc, beta_r=ALPHA_R, eps_k=EPS_K):
-    """Isotropic non-linear PG diffusivity, the paper's first residual-based form with the
-    mixed-mass residual estimate (section "Non-Linear Petrov-Galerkin Dissipation"):
+R_MIXED, R_LOW, R_HIGH = "mixed", "low", "high"
 
-        R = beta_r f(mu Psi_x + nu Psi_y; m_L^-1 m - I)
-        k_abs = akabs |R| h / (eps + (|Psi_x| + |Psi_y|) / D),                        D = 2
-        q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
-        k_square = aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|) / D (Psi_x^2 + Psi_y^2))
-        k_max = sqrt((dx mu)^2 + (dy nu)^2),   k = min(k_max, k_abs, k_square),   h = (dx + dy) / 2
 
-    on the interior; the same k acts in x and y: returns (k, k).  beta_r reads as alpha_r = 3."""
+def advection_estimate(psi, quad, dx, dy, p, bc):
+    """mu f(psi; w_x) + nu f(psi; w_y) with the ConvFEM filters of degree p, on the interior
+    (psi gets a halo of width p by the halo rule)."""
+    F = filters_2d(p, dx, dy)
+    ext = halo_extend(psi, quad["mu"], quad["nu"], p, bc)
+    mu = quad["mu"][None, :, None, None]
+    nu = quad["nu"][None, :, None, None]
+    return mu * apply_filter(ext, F["wx"]) + nu * apply_filter(ext, F["wy"])
+
+
+def isotropic_residual_estimate(psi, quad, dx, dy, p, bc, r_estimate=R_MIXED, beta_r=ALPHA_R):
+    """The residual estimate R of the isotropic diffusivity on the interior, one of the three of
+    section "Non-Linear Petrov-Galerkin Dissipation", with Psi_x = f(psi; w_x), Psi_y = f(psi; w_y)
+    of degree p:
+        mixed: R = beta_r f(mu Psi_x + nu Psi_y; m_L^-1 m - I)   (beta_r read as alpha_r = 3)
+        low:   R = (mu Psi_x + nu Psi_y) - (the same with the filters of degree p - 1),   p >= 2
+        high:  R = (the same with the filters of degree p + 1) - (mu Psi_x + nu Psi_y)
+    No coefficient is printed for the low and high estimates and none is applied.
+    Returns (R, Psi_x, Psi_y) on the interior."""
     F = filters_2d(p, dx, dy)
     Px, Py, _ = pg_gradients(psi, quad, dx, dy, p, bc)
     mu = quad["mu"][None, :, None, None]
     nu = quad["nu"][None, :, None, None]
     Px_i = Px[..., p:-p, p:-p]
     Py_i = Py[..., p:-p, p:-p]
-    adv = mu * Px + nu * Py
-    R = beta_r * (apply_filter(adv, F["wm"]) - adv[..., p:-p, p:-p])
+    if r_estimate == R_MIXED:
+        adv = mu * Px + nu * Py
+        R = beta_r * (apply_filter(adv, F["wm"]) - adv[..., p:-p, p:-p])
+    elif r_estimate == R_LOW:
+        if p < 2:
+            raise ValueError("the low-order residual estimate needs p >= 2")
+        R = (mu * Px_i + nu * Py_i) - advection_estimate(psi, quad, dx, dy, p - 1, bc)
+    elif r_estimate == R_HIGH:
+        R = advection_estimate(psi, quad, dx, dy, p + 1, bc) - (mu * Px_i + nu * Py_i)
+    else:
+        raise ValueError(r_estimate)
+    return R, Px_i, Py_i
+
+
+def pg_diffusivity_isotropic(psi, quad, dx, dy, p, bc, beta_r=ALPHA_R, eps_k=EPS_K, r_estimate=R_MIXED):
+    """Isotropic non-linear PG diffusivity, the paper's first residual-based form (section
+    "Non-Linear Petrov-Galerkin Dissipation"):
+
+        k_abs = akabs |R| h / (eps + (|Psi_x| + |Psi_y|) / D),                        D = 2
+        q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
+        k_square = aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|) / D (Psi_x^2 + Psi_y^2))
+        k_max = sqrt((dx mu)^2 + (dy nu)^2),   k = min(k_max, k_abs, k_square),   h = (dx + dy) / 2
+
+    on the interior, R from isotropic_residual_estimate.  The same k acts in x and y: returns (k, k)."""
+    R, Px_i, Py_i = isotropic_residual_estimate(psi, quad, dx, dy, p, bc, r_estimate, beta_r)
+    mu = quad["mu"][None, :, None, None]
+    nu = quad["nu"][None, :, None, None]
     h = 0.5 * (dx + dy)
     akabs, aksq = alpha_kabs(p), alpha_ksquare(p)
     k_abs = akabs * np.abs(R) * h / (eps_k + (np.abs(Px_i) + np.abs(Py_i)) / 2.0)
@@ -199,16 +235,20 @@ def k_diff(psi_ext_p, k, w, p):
     return apply_filter(k_ext * psi_ext_p, w) + k * apply_filter(psi_ext_p, w) - psi_i * apply_filter(k_ext, w)
 
 
-def pg_residual(psi, q, sigma_t, quad, dx, dy, p, bc, k=None, isotropic=False):
+def pg_residual(psi, q, sigma_t, quad, dx, dy, p, bc, k=None, isotropic=False, r_estimate=R_MIXED):
     """rho = q - mu Psi_x - nu Psi_y - kDiff_x - kDiff_y - sigma_t psi (lumped mass, w_ml = 1 in
     the per-unit-volume normalisation of the printed filters).
 
-    k = None: non-linear PG, k from psi (anisotropic, eq. ano-k; or the isotropic form).
+    k = None: non-linear PG, k from psi (anisotropic, eq. ano-k; or the isotropic form with the
+    residual estimate r_estimate).
     k = (kx, ky): frozen diffusivities.
     """
     F = filters_2d(p, dx, dy)
     if k is None:
-        k = (pg_diffusivity_isotropic if isotropic else pg_diffusivity)(psi, quad, dx, dy, p, bc)
+        if isotropic:
+            k = pg_diffusivity_isotropic(psi, quad, dx, dy, p, bc, r_estimate=r_estimate)
+        else:
+            k = pg_diffusivity(psi, quad, dx, dy, p, bc)
     kx, ky = k
     Px, Py, ext = pg_gradients(psi, quad, dx, dy, p, bc)
     mu = quad["mu"][None, :, None, None]

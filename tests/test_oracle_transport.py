@@ -250,3 +250,80 @@ def test_isotropic_pg_diffusivity_cubic_closed_form():
     ref = np.minimum(np.minimum(k_max, k_abs), k_sq)
     got = k[0, :, 2:-2, 2:-2]
     assert np.allclose(got, ref[:, None, :], rtol=1e-10, atol=1e-15)
+
+
+def _poly_field(N, h, deg, axis, G=1, nd=32):
+    c = (np.arange(N) + 0.5) * h
+    f = c ** deg
+    shape = (1, 1, 1, N) if axis == "x" else (1, 1, N, 1)
+    return np.broadcast_to(f.reshape(shape), (G, nd, N, N)).copy(), c
+
+
+# R for psi = x^deg (or y^deg) from the moments sum_u u^q d[u] of the 1D derivative stencils:
+# d_1 applied to x^3 gives 3x^2 + h^2; d_2 is exact on quintics less -4 h^4 (5x^4 - 4h^4 for x^5);
+# d_3 gives 5x^4 + 3h^4 for x^5; d_2, d_3 are exact on cubics and d_4 on quintics.  The mass
+# filter along the other axis acts on a constant (sum m = 1).
+@pytest.mark.parametrize("p,est,deg,coef,hp", [
+    (1, "high", 3, -1.0, 2),   # d_2 - d_1 on x^3: 3x^2 - (3x^2 + h^2)
+    (2, "low", 3, -1.0, 2),    # d_2 - d_1 on x^3
+    (3, "low", 5, 7.0, 4),     # d_3 - d_2 on x^5: (5x^4 + 3h^4) - (5x^4 - 4h^4)
+    (3, "high", 5, -3.0, 4),   # d_4 - d_3 on x^5: 5x^4 - (5x^4 + 3h^4)
+    (2, "high", 5, 7.0, 4),    # d_3 - d_2 on x^5, the pair of p = 3 low
+])
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_low_high_residual_estimates_closed_form(p, est, deg, coef, hp, axis):
+    """The low / high residual estimates of the isotropic diffusivity on psi = x^deg (or y^deg):
+    R = coef * (mu or nu) * h^hp on nodes whose filters stay inside the domain.  Pins which degree
+    is low and which high, the sign and the absence of a coefficient."""
+    from oracle.transport import isotropic_residual_estimate
+    quad = qd.quadrature(2)
+    N, h = 16, 0.25
+    psi, _ = _poly_field(N, h, deg, axis)
+    R, _, _ = isotropic_residual_estimate(psi, quad, h, h, p, ZG, r_estimate=est)
+    s = quad["mu"] if axis == "x" else quad["nu"]
+    ref = coef * s[:, None, None] * h ** hp
+    r = p + 1
+    got = R[0][:, r:-r, r:-r]
+    assert np.allclose(got, np.broadcast_to(ref, got.shape), rtol=1e-9, atol=1e-12 * h ** hp)
+
+
+def test_low_estimate_diffusivity_closed_form():
+    """psi = x^3, p = 2, low estimate: Psi_x = 3x^2 exactly, Psi_y = 0, R = -mu h^2; k from the
+    three bounds with akabs = 4/16, aksq = 4/2."""
+    from oracle.transport import pg_diffusivity_isotropic
+    quad = qd.quadrature(2)
+    mu, nu = quad["mu"][:, None], quad["nu"][:, None]
+    N, h, eps = 16, 0.3, 1e-3
+    psi, x = _poly_field(N, h, 3, "x")
+    k, _ = pg_diffusivity_isotropic(psi, quad, h, h, 2, ZG, r_estimate="low")
+    r = 3
+    xi = x[r:-r][None, :]
+    Px = 3 * xi ** 2
+    R = -mu * h ** 2
+    k_abs = 0.25 * np.abs(R) * h / (eps + Px / 2.0)
+    q = mu * Px / (eps + Px ** 2)
+    k_sq = 2.0 * R ** 2 * h / (eps + np.abs(q * Px) / 2.0 * Px ** 2)
+    k_max = h * np.sqrt(mu ** 2 + nu ** 2)
+    ref = np.minimum(np.minimum(k_max, k_abs), k_sq)
+    got = k[0][:, r:-r, r:-r]
+    assert np.allclose(got, np.broadcast_to(ref[:, None, :], got.shape), rtol=1e-10, atol=1e-15)
+
+
+def test_low_high_estimates_vanish_on_linear_fields():
+    """Every degree differentiates a linear field exactly, so both estimates vanish (and so does
+    k) away from the boundary; on a random field they differ from each other and from zero."""
+    from oracle.transport import isotropic_residual_estimate
+    quad = qd.quadrature(2)
+    N, h = 14, 0.2
+    c = (np.arange(N) + 0.5) * h
+    lin = np.broadcast_to((2.0 * c[None, :] - 0.7 * c[:, None] + 1.0)[None, None], (1, 32, N, N)).copy()
+    for p, est in ((2, "low"), (3, "low"), (1, "high"), (2, "high"), (3, "high")):
+        R, _, _ = isotropic_residual_estimate(lin, quad, h, h, p, ZG, r_estimate=est)
+        r = p + 1
+        assert np.abs(R[..., r:-r, r:-r]).max() < 1e-11, (p, est)
+    rng = np.random.default_rng(3)
+    psi = rng.uniform(0.0, 1.0, (1, 32, N, N))
+    Rl, _, _ = isotropic_residual_estimate(psi, quad, h, h, 2, VAC, r_estimate="low")
+    Rh, _, _ = isotropic_residual_estimate(psi, quad, h, h, 2, VAC, r_estimate="high")
+    assert np.abs(Rl).max() > 1e-3 and np.abs(Rh).max() > 1e-3
+    assert np.abs(Rl - Rh).max() > 1e-3
