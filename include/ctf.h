@@ -55,6 +55,8 @@ enum { CTF_FP64 = 0, CTF_FP32_IR = 1, CTF_FP32_IR_BF16_MOMENTS = 2 };
 enum { CTF_OP_APPLY = 0, CTF_OP_RESIDUAL = 1 };
 /* smoother kinds */
 enum { CTF_SMOOTH_UPWIND = 0, CTF_SMOOTH_FINEST = 1 };
+/* residual estimate R of the isotropic PG diffusivity (ctf_config.pg_r_estimate) */
+enum { CTF_R_MIXED_MASS = 0, CTF_R_LOW = 1, CTF_R_HIGH = 2 };
 
 typedef struct ctf_config {
   int n;               /* nodes per side of the finest grid (N x N), N >= 2 */
@@ -91,6 +93,16 @@ typedef struct ctf_config {
                             Petrov-Galerkin Dissipation": mixed-mass residual R, k = min(k_max, k_abs,
                             k_square), the same k in x and y) instead of the anisotropic pair of
                             eq. ano-k.  Default 0. */
+  int pg_r_estimate;     /* residual estimate R of the isotropic diffusivity (same section), with
+                            Psi_x = f(psi; w_x), Psi_y = f(psi; w_y) of degree p:
+                            CTF_R_MIXED_MASS: R = alpha_r f(mu Psi_x + nu Psi_y; m_L^-1 m - I);
+                            CTF_R_LOW: R = (mu Psi_x + nu Psi_y) minus the same with the filters of
+                            degree p - 1 (needs p >= 2);
+                            CTF_R_HIGH: R = the same with the filters of degree p + 1 minus
+                            (mu Psi_x + nu Psi_y) (needs p <= 3).  No factor on the low and high
+                            forms.  Other than CTF_R_MIXED_MASS needs pg_isotropic = 1; their
+                            diffusivities are formed in a pass of their own and stored (the fused
+                            launch shape does not apply).  Default CTF_R_MIXED_MASS. */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;

@@ -60,6 +60,14 @@ int validate(const ctf_config* c) {
   if (c->hemisphere != 0 && c->hemisphere != 1) return fail(CTF_EINVAL, "hemisphere 0 or 1");
   if (c->coupled_scatter != 0 && c->coupled_scatter != 1) return fail(CTF_EINVAL, "coupled_scatter 0 or 1");
   if (c->pg_isotropic != 0 && c->pg_isotropic != 1) return fail(CTF_EINVAL, "pg_isotropic 0 or 1");
+  if (c->pg_r_estimate < CTF_R_MIXED_MASS || c->pg_r_estimate > CTF_R_HIGH)
+    return fail(CTF_EINVAL, "pg_r_estimate must be CTF_R_MIXED_MASS, CTF_R_LOW or CTF_R_HIGH");
+  if (c->pg_r_estimate != CTF_R_MIXED_MASS && c->discretisation != CTF_UPWIND) {
+    if (!c->pg_isotropic) return fail(CTF_EINVAL, "the low / high residual estimates need pg_isotropic = 1");
+    if (c->pg_r_estimate == CTF_R_LOW && c->p < 2) return fail(CTF_EINVAL, "the low residual estimate needs p >= 2");
+    if (c->pg_r_estimate == CTF_R_HIGH && c->p + 1 > kMaxP)
+      return fail(CTF_EUNSUPPORTED, "the high residual estimate needs p <= 3 (filters of degree p + 1)");
+  }
   return CTF_OK;
 }
 
@@ -345,7 +353,7 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   if (frozen) {
     o.kx_in = P->kx;
     o.ky_in = P->ky;
-  } else if (k_float || !P->pg_fused) {
+  } else if (k_float || !P->pg_fused || P->pp.r_estimate) {
     o.kx_out = P->kx;
     o.ky_out = P->ky;
     if (k_float) {
@@ -531,7 +539,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   if (c.discretisation != CTF_CONVFEM_PG) {
     o.kx_in = P->kx_f;   // frozen k
     o.ky_in = P->ky_f;
-  } else if (!P->pg_fused) {
+  } else if (!P->pg_fused || P->pp.r_estimate) {
     o.kx_out = P->kx_f;  // full-approximation form: k of x itself, stored then read
     o.ky_out = P->ky_f;
   }
@@ -745,6 +753,7 @@ void ctf_default_config(ctf_config* c) {
   c->hemisphere = 0;
   c->coupled_scatter = 0;
   c->pg_isotropic = 0;
+  c->pg_r_estimate = CTF_R_MIXED_MASS;
 }
 
 size_t ctf_workspace_bytes(const ctf_config* cfg) {
@@ -794,6 +803,19 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
       P->st_f.k[i] = float(P->st_d.k[i]);
     }
   }
+  if (cfg->discretisation != CTF_UPWIND && cfg->pg_r_estimate != CTF_R_MIXED_MASS) {
+    // the other degree of the low / high residual estimate
+    const int q = cfg->pg_r_estimate == CTF_R_LOW ? p - 1 : p + 1;
+    double m[2 * kMaxP + 1], d[2 * kMaxP + 1], k[2 * kMaxP + 1];
+    convfem_stencils(q, m, d, k);
+    for (int i = 0; i < 2 * kMaxP + 1; ++i) {
+      const bool in = i < 2 * q + 1;
+      P->st_d.mr[i] = in ? m[i] : 0.0;
+      P->st_d.dr[i] = in ? d[i] / h0 : 0.0;
+      P->st_f.mr[i] = float(P->st_d.mr[i]);
+      P->st_f.dr[i] = float(P->st_d.dr[i]);
+    }
+  }
   P->pp.alpha_r = cfg->alpha_r;
   P->pp.eps_k = cfg->eps_k;
   P->pp.alpha_kabs = std::pow(2.0, p) / 16.0;
@@ -801,6 +823,7 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   P->pp.beta = cfg->beta_pg;
   P->pp.bc_vac = P->bc_vac;
   P->pp.isotropic = cfg->pg_isotropic;
+  P->pp.r_estimate = cfg->discretisation == CTF_UPWIND ? 0 : cfg->pg_r_estimate;
 
   hipStream_t s = P->stream;
   auto bail = [&](int code) {

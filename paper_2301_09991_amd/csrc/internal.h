@@ -45,6 +45,8 @@ struct Stencils {
   T m[2 * kMaxP + 1];
   T d[2 * kMaxP + 1];  // already divided by h
   T k[2 * kMaxP + 1];  // already divided by h^2
+  T mr[2 * kMaxP + 1]; // m and d (divided by h) of the other degree of the low / high residual
+  T dr[2 * kMaxP + 1]; // estimate (degree p - 1 or p + 1), zero otherwise
 };
 
 struct LevelDims {
@@ -70,6 +72,7 @@ struct PGParams {
   double alpha_r, eps_k, alpha_kabs, alpha_ksq, beta;
   int bc_vac;
   int isotropic = 0;   // 1: the isotropic diffusivity (k_x = k_y) instead of the anisotropic pair
+  int r_estimate = 0;  // its residual estimate: 0 mixed mass, 1 degree p - 1, 2 degree p + 1
 };
 
 // ---- kernel launchers (kernels.hip) ------------------------------------------------------------

@@ -278,6 +278,7 @@ struct PGArgs {
   float* kx_out_f;    // optional float copies of the computed diffusivities
   float* ky_out_f;
   int iso;            // isotropic diffusivity
+  int r_estimate;     // its residual estimate (0 mixed mass, 1 degree p - 1, 2 degree p + 1)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -485,10 +486,19 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
 //   Psi_x = f(psi; m (x) d), Psi_y = f(psi; d (x) m) (psi with its halo rule),
 //   R = alpha_r mu (f(Psi; m (x) m) - Psi),  k = min(h|mu|, akabs |R| h/(eps+|Psi|), aksq R^2 h/(eps+|mu| Psi^2)).
 // The strip reads 64 + 4P columns, and writes k for its inner 64 - 2P columns.
-template <int P, typename T>
+// RE selects the residual estimate of the isotropic form: 0 the mixed mass (above), 1 / 2 the
+// difference of the advection estimates mu Psi_x + nu Psi_y of degrees P and P - 1 / P + 1 (section
+// "Non-Linear Petrov-Galerkin Dissipation").  The other degree Q = P -+ 1 is x-passed on every
+// psi row into windows of 2P + Q + 1 rows, long enough to reach back to row o - Q when row o is
+// written.
+template <int P, int RE, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
+  static_assert(RE == 0 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP), "residual estimate degree");
   constexpr int W = 2 * P + 1;
+  constexpr int PQ = RE == 1 ? P - 1 : (RE == 2 ? P + 1 : 0);   // the other degree
+  constexpr int WQ = 2 * PQ + 1;
+  constexpr int KQ = RE ? 2 * P + PQ + 1 : 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
   constexpr int D = P + 2;              // LDS ring of Psi rows: the newest and the P rows above it
@@ -511,8 +521,16 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
     cm[t] = a.st.m[t];
     cd[t] = a.st.d[t];
   }
+  T cmq[WQ], cdq[WQ];
+#pragma unroll
+  for (int t = 0; t < WQ; ++t) {
+    cmq[t] = a.st.mr[t];
+    cdq[t] = a.st.dr[t];
+  }
   // rotating windows (slot = step % W): x-passes of psi rows, x-passes of Psi rows
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
+  // shifted windows (newest row last) of the other degree's x-passes
+  T wQd[KQ] = {}, wQm[KQ] = {};
   const int c0 = x0 - P + lane, c1 = c0 + kStripW;
   const int cc0 = clampi(c0, 0, n - 1), cc1 = clampi(c1, 0, n - 1);
   const bool zx0 = (c0 < 0 && (a.bc_vac & 1) && mu > T(0)) || (c0 >= n && (a.bc_vac & 2) && mu < T(0));
@@ -553,34 +571,63 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       }
       wXd[t] = xd;
       wXm[t] = xm;
+      if constexpr (RE != 0) {
+        // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row buffer; lq = lane for
+        // every lane that writes
+        const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
+        T qd = 0, qm = 0;
+#pragma unroll
+        for (int u = 0; u < WQ; ++u) {
+          const T v = s_psi[lq + P - PQ + u];
+          qd += cdq[u] * v;
+          qm += cmq[u] * v;
+        }
+        push(wQd, qd);
+        push(wQm, qm);
+      }
       // Psi on row r - P (meaningful once the window is full)
       T* const gxr = s_g[ring][0];
       T* const gyr = s_g[ring][1];
       gxr[lane] = yrot(wXd, cm, t);
       gyr[lane] = yrot(wXm, cd, t);
       __syncthreads();
-      T mx = 0, my = 0;
-      if (lane >= P && lane < kStripW - P) {
+      if constexpr (RE == 0) {
+        T mx = 0, my = 0;
+        if (lane >= P && lane < kStripW - P) {
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-          mx += cm[u] * gxr[lane - P + u];
-          my += cm[u] * gyr[lane - P + u];
+          for (int u = 0; u < W; ++u) {
+            mx += cm[u] * gxr[lane - P + u];
+            my += cm[u] * gyr[lane - P + u];
+          }
         }
+        wMx[t] = mx;
+        wMy[t] = my;
       }
-      wMx[t] = mx;
-      wMy[t] = my;
       const int o = r - 2 * P;
       if (o >= y0 && writer) {
         const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of Psi row o
         const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
-        const T rx = ar * mu * (yrot(wMx, cm, t) - px);
-        const T ry = ar * nu * (yrot(wMy, cm, t) - py);
         T kx, ky;
-        if (a.iso) {
-          kx = ky = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+        if constexpr (RE != 0) {
+          // Psi of the other degree on row o: y-pass over the window rows o - Q .. o + Q
+          T qx = 0, qy = 0;
+#pragma unroll
+          for (int v = 0; v < WQ; ++v) {
+            qx += cmq[v] * wQd[v];
+            qy += cdq[v] * wQm[v];
+          }
+          const T adv = mu * px + nu * py, advq = mu * qx + nu * qy;
+          const T R = RE == 1 ? adv - advq : advq - adv;
+          kx = ky = pg_k_iso(mu, nu, R, px, py, h, akabs, aksq, eps);
         } else {
-          kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
-          ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+          if (a.iso) {
+            kx = ky = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+          } else {
+            kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
+            ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+          }
         }
         const size_t ro = base + size_t(o) * n;
         if (a.kx_out) {
@@ -1217,6 +1264,7 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
   a.beta = T(pp.beta);
   a.bc_vac = pp.bc_vac;
   a.iso = pp.isotropic;
+  a.r_estimate = pp.r_estimate;
   a.psi = o.psi;
   a.E = o.E;
   a.nmomE = o.nmomE;
@@ -1240,11 +1288,18 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
   const int ow = kStripW - 2 * p;
   a.ntx = (n + ow - 1) / ow;
   const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
-  switch (p) {
-    case 1: hipLaunchKernelGGL((k_pg_diffusivity<1, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pg_diffusivity<2, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pg_diffusivity<3, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pg_diffusivity<4, T>), grid, dim3(kStripW), 0, s, a); break;
+  if (pp.r_estimate && !pp.isotropic) return hipErrorInvalidValue;
+  switch (p * 4 + pp.r_estimate) {
+    case 4: hipLaunchKernelGGL((k_pg_diffusivity<1, 0, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_pg_diffusivity<2, 0, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 12: hipLaunchKernelGGL((k_pg_diffusivity<3, 0, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_pg_diffusivity<4, 0, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 9: hipLaunchKernelGGL((k_pg_diffusivity<2, 1, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 13: hipLaunchKernelGGL((k_pg_diffusivity<3, 1, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 17: hipLaunchKernelGGL((k_pg_diffusivity<4, 1, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 6: hipLaunchKernelGGL((k_pg_diffusivity<1, 2, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 10: hipLaunchKernelGGL((k_pg_diffusivity<2, 2, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 14: hipLaunchKernelGGL((k_pg_diffusivity<3, 2, T>), grid, dim3(kStripW), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1256,7 +1311,8 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
-    // fused: the diffusivities of psi are formed on the fly
+    // fused: the diffusivities of psi are formed on the fly (mixed-mass estimate only)
+    if (pp.r_estimate) return hipErrorInvalidValue;
     a.out = o.out;
     a.out_f = o.out_f;
     a.partial = o.partial;

@@ -17,6 +17,7 @@ VACUUM, ZERO_GRADIENT = 0, 1
 FP64, FP32_IR, FP32_IR_BF16_MOMENTS = 0, 1, 2
 OP_APPLY, OP_RESIDUAL = 0, 1
 SMOOTH_UPWIND, SMOOTH_FINEST = 0, 1
+R_MIXED_MASS, R_LOW, R_HIGH = 0, 1, 2
 
 EXPORTED = [
     "ctf_default_config", "ctf_workspace_bytes", "ctf_create_problem", "ctf_destroy_problem",
@@ -41,6 +42,7 @@ class Config(ctypes.Structure):
         ("alpha_r", ctypes.c_double), ("eps_k", ctypes.c_double), ("n_inner", ctypes.c_int),
         ("cnn_level", ctypes.c_int), ("cnn_max_growth", ctypes.c_double), ("cnn_max_uses", ctypes.c_int),
         ("hemisphere", ctypes.c_int), ("coupled_scatter", ctypes.c_int), ("pg_isotropic", ctypes.c_int),
+        ("pg_r_estimate", ctypes.c_int),
     ]
 
 

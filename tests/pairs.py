@@ -17,19 +17,21 @@ def workload(N=40, na=2, G=1, scatter="iso", p=2, L=1.0, patch=8, seed=11, sourc
 
 
 def make_pair(w, disc="pg", bc="vac", precision=0, n_jacobi=2, n_pg=2, n_inner=2, max_levels=0,
-              hemisphere=False, coupled=False, isotropic=False):
+              hemisphere=False, coupled=False, isotropic=False, r_estimate="mixed"):
     from paper_2301_09991_amd import ctf
     st, ss, src = make_inputs(w)
     od, cd = DISC[disc]
     bcs = BCS[bc]
     oprob = omg.Problem(w.N, w.L, w.p, w.na, st, ss, src, bc=bcs, disc=od, n_jacobi=n_jacobi,
-                        n_pg=n_pg, max_levels=max_levels, coupled=coupled, isotropic=isotropic)
+                        n_pg=n_pg, max_levels=max_levels, coupled=coupled, isotropic=isotropic,
+                        r_estimate=r_estimate)
     cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
                              scatter_order=ss.shape[0] - 1, discretisation=cd,
                              bc=[0 if b == VACUUM else 1 for b in bcs], precision=precision,
                              n_jacobi=n_jacobi, n_pg=n_pg, n_inner=n_inner, max_levels=max_levels,
                              hemisphere=int(hemisphere), coupled_scatter=int(coupled),
-                             pg_isotropic=int(isotropic))
+                             pg_isotropic=int(isotropic),
+                             pg_r_estimate={"mixed": 0, "low": 1, "high": 2}[r_estimate])
     gprob = ctf.Problem(cfg, st, ss, src)
     return oprob, gprob
 

@@ -58,6 +58,15 @@ def test_config_validation():
         ctf.workspace_bytes(ctf.default_config(n_jacobi=0))
     with pytest.raises(ctf.CtfError):
         ctf.convfem_stencils(0)
+    # residual estimates: low needs p >= 2, high p <= 3, both the isotropic diffusivity
+    pg = dict(discretisation=ctf.CONVFEM_PG, pg_isotropic=1)
+    for bad in (dict(pg, p=1, pg_r_estimate=ctf.R_LOW), dict(pg, p=4, pg_r_estimate=ctf.R_HIGH),
+                dict(pg, p=2, pg_r_estimate=3), dict(pg, p=2, pg_isotropic=0, pg_r_estimate=ctf.R_LOW)):
+        with pytest.raises(ctf.CtfError):
+            ctf.workspace_bytes(ctf.default_config(**bad))
+    for good in (dict(pg, p=2, pg_r_estimate=ctf.R_LOW), dict(pg, p=4, pg_r_estimate=ctf.R_LOW),
+                 dict(pg, p=1, pg_r_estimate=ctf.R_HIGH), dict(pg, p=3, pg_r_estimate=ctf.R_HIGH)):
+        assert ctf.workspace_bytes(ctf.default_config(**good)) > 0
     small = ctf.workspace_bytes(ctf.default_config(n=32))
     big = ctf.workspace_bytes(ctf.default_config(n=64))
     assert 3.5 * small < big < 4.5 * small
