@@ -510,9 +510,11 @@ int cycle_rest64(ctf_problem* P, double* psi, bool use_cnn = false, bool feature
 // float32 fixed point is the float64 one up to float32 rounding, which the float64 refinement
 // removes.
 
-// float32 finest operator on x (emission of x without source, per-DOF term r_f):
-//   mode 0: out = sign (r_f + q(x) - L x);  mode 1: out = x + (r_f + q(x) - L x)/(beta d)
-int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float sign = 1.0f) {
+// float32 finest operator on x (emission of x without source, per-DOF term r = rsign rhs, rhs = r_f
+// unless given):
+//   mode 0: out = sign (r + q(x) - L x);  mode 1: out = x + (r + q(x) - L x)/(beta d)
+int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float sign = 1.0f,
+                   const float* rhs = nullptr, float rsign = 1.0f) {
   const ctf_config& c = P->cfg;
   const int nl = c.scatter_order + 1;
   if (c.precision == CTF_FP32_IR_BF16_MOMENTS) {
@@ -527,6 +529,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
     CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
   }
   if (c.discretisation == CTF_UPWIND) {
+    if (rhs || rsign != 1.0f) return fail(CTF_EUNSUPPORTED, "internal: upwind float32 operator with another rhs");
     Timed t(P, CTF_T_UPWIND32);
     CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, x, P->E_f, P->nmom, out, mode, sign,
                                       P->r_f, P->stream));
@@ -544,20 +547,22 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
     o.ky_out = P->ky_f;
   }
   o.out = out;
-  o.rhs = P->r_f;
+  o.rhs = rhs ? rhs : P->r_f;
+  o.rhs_sign = rsign;
   o.mode = mode;
   o.sign = sign;
   o.strip_h = P->strip_h;
   return run_pg<float>(P, CTF_T_PG32, CTF_T_PGK32, P->lf(0), P->st_f, o);
 }
 
-// one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0)
-int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false) {
+// one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0);
+// r0_given: P->rho_f[0] already holds the finest residual of e_f
+int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false, bool r0_given = false) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
   // inner residual r - A e (just r while e = 0)
-  const float* r0 = P->r_f;
-  if (!e_is_zero) {
+  const float* r0 = r0_given ? P->rho_f[0] : P->r_f;
+  if (!e_is_zero && !r0_given) {
     int rc = inner_finest32(P, P->e_f, P->rho_f[0], 0);
     if (rc) return rc;
     r0 = P->rho_f[0];
@@ -599,15 +604,15 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false) {
   return CTF_OK;
 }
 
-// Float64 residual of psi and its norm.  r_f receives rho64 rounded to float32 (linear forms) or
-// -rho64 (full-approximation form, see refine_rest).  Returns ||rho||_W / ||b||_W through rel.
+// Float64 residual of psi and its norm.  rho64 rounded to float32 goes to r_f (linear forms) or
+// to rho_f[0] (full-approximation form, see refine_rest).  Returns ||rho||_W / ||b||_W through rel.
 // the float64 residual and its squared norm (in P->scal[0]) without synchronising
 int outer_residual_async(ctf_problem* P, const double* psi) {
   int rc = emission64(P, psi, true);
   if (rc) return rc;
   const int disc = P->cfg.discretisation;
   const size_t n = P->dof(0);
-  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, -1.0, P->r_f, true, false);
+  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, 1.0, P->rho_f[0], true, false);
   rc = finest64(P, psi, nullptr, 0, 1.0, P->r_f, true, false);
   if (rc) return rc;
   if (disc == CTF_CONVFEM_PG_FROZEN_K) {
@@ -632,15 +637,18 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   const size_t n = P->dof(0);
   const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
   if (fas) {
-    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 (in place over r_f = -rho64)
+    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 into r_f, with rho64 rounded in rho_f[0]:
+    // b32 = -(-rho64 + q(u) - L u)
     CTF_HIP(launch_convert_d2f(psi, P->e_f, n, P->stream, P->active));
-    int rc = inner_finest32(P, P->e_f, P->r_f, 0, -1.0f);
+    int rc = inner_finest32(P, P->e_f, P->r_f, 0, -1.0f, P->rho_f[0], -1.0f);
     if (rc) return rc;
   }
   int it = 0;
   for (; it < P->cfg.n_inner && it < max_inner; ++it) {
-    // the learned correction acts in the first float32 cycle of a refinement step only
-    int rc = inner_cycle32(P, !fas && it == 0, use_cnn && it == 0);
+    // The learned correction acts in the first float32 cycle of a refinement step only.  In the
+    // full-approximation form the first cycle's residual b32 - A32(psi32) is rho64 up to float32
+    // rounding, and rho64 rounded (in rho_f[0]) is taken for it.
+    int rc = inner_cycle32(P, !fas && it == 0, use_cnn && it == 0, fas && it == 0);
     if (rc) return rc;
   }
   if (it > 0) {

@@ -113,6 +113,7 @@ struct PGLaunch {
   float* kx_out_f = nullptr;
   float* ky_out_f = nullptr;
   const T* rhs = nullptr;
+  T rhs_sign = T(1);  // the rhs enters as rhs_sign * rhs (+1 or -1)
   int mode = 0;
   T sign = T(1);
   int strip_h = 32;   // rows per wavefront strip (tunable)

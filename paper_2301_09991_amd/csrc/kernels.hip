@@ -269,6 +269,7 @@ struct PGArgs {
   T* kx_out;
   T* ky_out;
   const T* rhs;
+  T rhs_sign;         // the rhs enters as rhs_sign * rhs (+1 or -1)
   int mode;
   T sign;
   int ntx;
@@ -332,7 +333,7 @@ __device__ __forceinline__ T yrot(const T (&w)[W], const T* c, int t) {
 }
 
 // Residual with given diffusivities (k_x, k_y read with a copied halo):
-//   rho = rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
+//   rho = rhs_sign rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
 //   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
 template <int P, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
@@ -377,6 +378,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   T p0, k0, q0, p1, k1, q1;
   T fe0, fe1, fe2, frh, fs;   // emission moments, rhs, sigma_t of output row r - P
   const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
+  const T rsg = a.rhs_sign;
   const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
   const T* __restrict__ E1g = p1mom ? Eg + ncell : Eg;
   const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
@@ -452,7 +454,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
         const size_t ro = base + size_t(o) * n;
         T q = e0;
         if (p1mom) q += mu * e1 + nu * e2;
-        if (has_rhs) q += rh;
+        if (has_rhs) q = __builtin_fma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
         if (a.mode == 0) {
           const T val = a.sign * rho;
@@ -717,6 +719,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   // use), so that no join waits for a load in flight
   T p0, p1, fe0, fe1, fe2, frh, fs;
   const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
+  const T rsg = a.rhs_sign;
   const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
   const T* __restrict__ E1g = p1mom ? Eg + ncell : Eg;
   const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         const size_t ro = base + size_t(o) * n;
         T q = e0;
         if (p1mom) q += mu * e1 + nu * e2;
-        if (has_rhs) q += rh;
+        if (has_rhs) q = __builtin_fma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
         if (a.mode == 0) {
           const T val = a.sign * rho;
@@ -1269,6 +1272,7 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
   a.E = o.E;
   a.nmomE = o.nmomE;
   a.rhs = o.rhs;
+  a.rhs_sign = o.rhs_sign;
   a.mode = o.mode;
   a.sign = o.sign;
   a.strip_h = o.strip_h;
