@@ -422,9 +422,20 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
   const int ndc = (l + 1 < P->L) ? P->dims[l + 1].nd : 1;   // ordinates of the next coarser level
   const T* cur = xsrc;
   int mode = xmode;
-  for (int s = 0; s < nsweeps; ++s) {
-    const bool last = s == nsweeps - 1;
-    T* dst = (last && final) ? final : ((s % 2 == 0) ? bufa : bufb);
+  for (int s = 0, pass = 0; s < nsweeps; ++pass) {
+    // without the scattering term, two sweeps run as one pass; passes alternate between the buffers
+    const bool pair = !P->cfg.coupled_scatter && s + 1 < nsweeps;
+    const bool last = s + (pair ? 2 : 1) == nsweeps;
+    T* dst = (last && final) ? final : ((pass % 2 == 0) ? bufa : bufb);
+    if (pair) {
+      Timed t(P, l == 0 ? CTF_T_CORR0 : CTF_T_CORRC);
+      CTF_HIP(launch_upwind_correction2<T>(L, P->bc_vac, cur, mode, ndc, rhs, dst, (last && acc) ? acc : nullptr,
+                                           P->stream, P->corr_block));
+      cur = dst;
+      mode = 0;
+      s += 2;
+      continue;
+    }
     const T* Esc = nullptr;
     if (P->cfg.coupled_scatter && mode != 2) {
       Timed t(P, CTF_T_CSCAT);
@@ -444,6 +455,7 @@ int correction_sweeps(ctf_problem* P, const LevelData<T>& L, int l, const T* xsr
                                         P->nmom));
     cur = dst;
     mode = 0;
+    ++s;
   }
   if (result) *result = cur;
   return CTF_OK;

@@ -152,6 +152,12 @@ template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
                                     int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
                                     int block = 256, const T* E = nullptr, int nmomE = 1);
+// Two such sweeps (without the scattering term) in one pass: the first from (x_in, xmode), the
+// second from its result; the result as for one sweep.
+template <typename T>
+hipError_t launch_upwind_correction2(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
+                                     int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s,
+                                     int block = 256);
 
 template <typename T>
 hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine,
