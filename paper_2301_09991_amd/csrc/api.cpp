@@ -264,7 +264,7 @@ size_t layout(ctf_problem* P, char* base) {
   }
   P->npartial = wnorm2_partials(P->dims[0]);
   P->partial_cap = std::max<size_t>({size_t(P->npartial), pg_partials(P->dims[0], 8), upwind_full_blocks(P->dims[0])});
-  P->partial = c.take<double>(P->partial_cap);
+  P->partial = c.take<double>(P->partial_cap + sum_partials_extra());
   P->scal = c.take<double>(8);
   P->active = c.take<int>(64);
   for (int l = 0; l < P->L; ++l) P->dims[l].active = P->active;

@@ -1239,6 +1239,25 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+// first stage of a long sum: block b adds the b-th of kSumBlocks contiguous chunks (fixed order)
+constexpr int kSumBlocks = 256;
+__global__ __launch_bounds__(kBlock) void k_sum_chunks(const double* __restrict__ partial, int np,
+                                                        double* __restrict__ stage, const int* active) {
+  if (idle(active)) return;
+  __shared__ double red[kBlock];
+  const int chunk = (np + kSumBlocks - 1) / kSumBlocks;
+  const int beg = int(blockIdx.x) * chunk, end = min(beg + chunk, np);
+  double acc = 0.0;
+  for (int i = beg + int(threadIdx.x); i < end; i += kBlock) acc += partial[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) stage[blockIdx.x] = red[0];
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy(T* __restrict__ y, const T* __restrict__ x, T a,
                                                   size_t n, const int* active) {
@@ -1545,8 +1564,17 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
   return hipGetLastError();
 }
 
+int sum_partials_extra() { return kSumBlocks; }
+
 hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s, const int* active) {
-  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, np, out, active);
+  if (np > 16 * kBlock) {
+    // two stages: kSumBlocks chunk sums after the np partials, then their sum
+    double* stage = const_cast<double*>(partial) + np;
+    hipLaunchKernelGGL(k_sum_chunks, dim3(kSumBlocks), dim3(kBlock), 0, s, partial, np, stage, active);
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, stage, kSumBlocks, out, active);
+  } else {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, np, out, active);
+  }
   return hipGetLastError();
 }
 
