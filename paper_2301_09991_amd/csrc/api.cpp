@@ -145,6 +145,7 @@ struct ctf_problem {
   int strip_h = 128;         // launch shapes (defaults: fastest measured on the 256^2 p = 2 workload)
   int corr_block = 256;
   int pg_fused = 1;          // non-linear PG: diffusivities formed in the same pass (1) or stored (0)
+  bool psi32_ready = false;  // e_f holds psi rounded to float (left by the outer residual)
   // learned coarse-grid correction
   int cnn_level = -1;
   bool cnn_on = false;
@@ -326,11 +327,13 @@ int run_pg(ctf_problem* P, int cls, int cls_k, const LevelData<T>& L, const Sten
 // Finest operator with the emission already in E.
 //   mode 0: out = sign * rho(psi) (out and / or out_f), with the squared weighted norm summed into
 //           P->scal[0] when want_norm; mode 1: out = psi + rho / (beta d).
-//   kf: float copies of the diffusivities computed from psi (mixed precision), or null.
+//   k_float: also float copies of the diffusivities computed from psi (mixed precision);
+//   psi_f: psi rounded to float (PG forms), or null.
 int finest64(ctf_problem* P, const double* psi, double* out, int mode, double sign,
-             float* out_f = nullptr, bool want_norm = false, bool k_float = false) {
+             float* out_f = nullptr, bool want_norm = false, bool k_float = false, float* psi_f = nullptr) {
   const ctf_config& c = P->cfg;
   if (c.discretisation == CTF_UPWIND) {
+    if (psi_f) return fail(CTF_EUNSUPPORTED, "internal: float copy of psi from the upwind operator");
     double* partial = (mode == 0 && want_norm) ? P->partial : nullptr;
     int np = 0;
     {
@@ -366,6 +369,7 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   o.mode = mode;
   o.sign = sign;
   o.partial = (mode == 0 && want_norm) ? P->partial : nullptr;
+  o.psi_f = psi_f;
   o.strip_h = P->strip_h;
   int np = 0;
   o.npartial = &np;
@@ -526,7 +530,7 @@ int cycle_rest64(ctf_problem* P, double* psi, bool use_cnn = false, bool feature
 // unless given):
 //   mode 0: out = sign (r + q(x) - L x);  mode 1: out = x + (r + q(x) - L x)/(beta d)
 int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float sign = 1.0f,
-                   const float* rhs = nullptr, float rsign = 1.0f) {
+                   const float* rhs = nullptr, float rsign = 1.0f, double* acc64 = nullptr) {
   const ctf_config& c = P->cfg;
   const int nl = c.scatter_order + 1;
   if (c.precision == CTF_FP32_IR_BF16_MOMENTS) {
@@ -541,7 +545,8 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
     CTF_HIP(launch_emission<float>(P->dims[0], P->phi_f, P->sigma_s_f, nl, nullptr, P->E_f, P->stream));
   }
   if (c.discretisation == CTF_UPWIND) {
-    if (rhs || rsign != 1.0f) return fail(CTF_EUNSUPPORTED, "internal: upwind float32 operator with another rhs");
+    if (rhs || rsign != 1.0f || acc64)
+      return fail(CTF_EUNSUPPORTED, "internal: upwind float32 operator with another rhs or a float64 update");
     Timed t(P, CTF_T_UPWIND32);
     CTF_HIP(launch_upwind_full<float>(P->lf(0), P->bc_vac, x, P->E_f, P->nmom, out, mode, sign,
                                       P->r_f, P->stream));
@@ -561,6 +566,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   o.out = out;
   o.rhs = rhs ? rhs : P->r_f;
   o.rhs_sign = rsign;
+  o.acc64 = acc64;
   o.mode = mode;
   o.sign = sign;
   o.strip_h = P->strip_h;
@@ -568,8 +574,10 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
 }
 
 // one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0);
-// r0_given: P->rho_f[0] already holds the finest residual of e_f
-int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false, bool r0_given = false) {
+// r0_given: P->rho_f[0] already holds the finest residual of e_f; psi64: the last finest sweep
+// also applies the full-approximation update psi64 += u - float(psi64) with its result u
+int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false, bool r0_given = false,
+                  double* psi64 = nullptr) {
   const ctf_config& c = P->cfg;
   const int L = P->L;
   // inner residual r - A e (just r while e = 0)
@@ -608,7 +616,7 @@ int inner_cycle32(ctf_problem* P, bool e_is_zero, bool use_cnn = false, bool r0_
   float* cur = P->e_f;
   float* other = P->e_tmp_f;
   for (int s = 0; s < c.n_pg; ++s) {
-    int rc = inner_finest32(P, cur, other, 1);
+    int rc = inner_finest32(P, cur, other, 1, 1.0f, nullptr, 1.0f, s == c.n_pg - 1 ? psi64 : nullptr);
     if (rc) return rc;
     std::swap(cur, other);
   }
@@ -624,7 +632,12 @@ int outer_residual_async(ctf_problem* P, const double* psi) {
   if (rc) return rc;
   const int disc = P->cfg.discretisation;
   const size_t n = P->dof(0);
-  if (disc == CTF_CONVFEM_PG) return finest64(P, psi, nullptr, 0, 1.0, P->rho_f[0], true, false);
+  if (disc == CTF_CONVFEM_PG) {
+    // the same pass leaves psi rounded to float in e_f for refine_rest
+    rc = finest64(P, psi, nullptr, 0, 1.0, P->rho_f[0], true, false, P->e_f);
+    P->psi32_ready = rc == CTF_OK;
+    return rc;
+  }
   rc = finest64(P, psi, nullptr, 0, 1.0, P->r_f, true, false);
   if (rc) return rc;
   if (disc == CTF_CONVFEM_PG_FROZEN_K) {
@@ -649,23 +662,31 @@ int refine_rest(ctf_problem* P, double* psi, int max_inner, int* done, bool use_
   const size_t n = P->dof(0);
   const bool fas = P->cfg.discretisation == CTF_CONVFEM_PG;
   if (fas) {
-    // u = psi32 = psi64 rounded; b32 = A32(psi32) + rho64 into r_f, with rho64 rounded in rho_f[0]:
-    // b32 = -(-rho64 + q(u) - L u)
-    CTF_HIP(launch_convert_d2f(psi, P->e_f, n, P->stream, P->active));
+    // u = psi32 = psi64 rounded (left in e_f by the outer residual); b32 = A32(psi32) + rho64 into
+    // r_f, with rho64 rounded in rho_f[0]: b32 = -(-rho64 + q(u) - L u)
+    if (!P->psi32_ready) CTF_HIP(launch_convert_d2f(psi, P->e_f, n, P->stream, P->active));
+    P->psi32_ready = false;
     int rc = inner_finest32(P, P->e_f, P->r_f, 0, -1.0f, P->rho_f[0], -1.0f);
     if (rc) return rc;
   }
+  const int n_run = std::max(0, std::min(P->cfg.n_inner, max_inner));
+  // full-approximation form: the last finest sweep of the last cycle applies psi += u - fl32(psi)
+  const bool fused_update = fas && P->cfg.n_pg > 0;
   int it = 0;
-  for (; it < P->cfg.n_inner && it < max_inner; ++it) {
+  for (; it < n_run; ++it) {
     // The learned correction acts in the first float32 cycle of a refinement step only.  In the
     // full-approximation form the first cycle's residual b32 - A32(psi32) is rho64 up to float32
     // rounding, and rho64 rounded (in rho_f[0]) is taken for it.
-    int rc = inner_cycle32(P, !fas && it == 0, use_cnn && it == 0, fas && it == 0);
+    int rc = inner_cycle32(P, !fas && it == 0, use_cnn && it == 0, fas && it == 0,
+                           fused_update && it + 1 == n_run ? psi : nullptr);
     if (rc) return rc;
   }
   if (it > 0) {
-    if (fas) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, n, P->stream, P->active));   // psi += u - fl32(psi)
-    else CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream, P->active));
+    if (fas) {
+      if (!fused_update) CTF_HIP(launch_add_diff_f2d(psi, P->e_f, n, P->stream, P->active));   // psi += u - fl32(psi)
+    } else {
+      CTF_HIP(launch_add_f2d(psi, P->e_f, n, P->stream, P->active));
+    }
   }
   if (done) *done = it;
   return CTF_OK;

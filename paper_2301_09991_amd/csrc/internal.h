@@ -118,6 +118,8 @@ struct PGLaunch {
   T sign = T(1);
   int strip_h = 32;   // rows per wavefront strip (tunable)
   int* npartial = nullptr;  // receives the number of per-block partial sums written (mode 0)
+  float* psi_f = nullptr;   // optional: psi rounded to float at the output cells
+  double* acc64 = nullptr;  // mode 1, optional: acc64 += out - float(acc64) at the output cells
 };
 // Residual / sweep of the ConvFEM-PG operator.  With neither kx_in nor kx_out the non-linear
 // diffusivities are formed inside the one pass; with kx_out (and no kx_in) they are formed by

@@ -278,6 +278,8 @@ struct PGArgs {
   double* partial;    // optional per-block sum of w_n h^2 out^2 (mode 0)
   float* kx_out_f;    // optional float copies of the computed diffusivities
   float* ky_out_f;
+  float* psi_f;       // optional float copy of psi at the output cells
+  double* acc64;      // mode 1, optional: acc64 += out - float(acc64) at the output cells
   int iso;            // isotropic diffusivity
   int r_estimate;     // its residual estimate (0 mixed mass, 1 degree p - 1, 2 degree p + 1)
 };
@@ -456,13 +458,19 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
         if (p1mom) q += mu * e1 + nu * e2;
         if (has_rhs) q = __builtin_fma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
+        if (a.psi_f) at(a.psi_f + ro, bof) = float(pc);
         if (a.mode == 0) {
           const T val = a.sign * rho;
           if (a.out) at(a.out + ro, bo) = val;
           if (a.out_f) at(a.out_f + ro, bof) = float(val);
           acc += double(val) * double(val);
         } else {
-          at(a.out + ro, bo) = pc + qdiv(rho, diag + a.beta * sig);
+          const T un = pc + qdiv(rho, diag + a.beta * sig);
+          at(a.out + ro, bo) = un;
+          if (a.acc64) {
+            double& y = at(a.acc64 + ro, unsigned(gi) * 8u);
+            y = y + (double(un) - double(float(y)));
+          }
         }
       }
       ring = ring + 1 == D ? 0 : ring + 1;
@@ -664,7 +672,8 @@ __device__ __forceinline__ int ring_slot(int row, int depth) {
 __device__ __forceinline__ int ring_back(int s, int off, int depth) { return s >= off ? s - off : s - off + depth; }
 __device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == depth ? 0 : s + 1; }
 
-template <int P, typename T>
+// ACC: a.acc64 is given (mode 1), its values are prefetched with the other per-cell data.
+template <int P, typename T, bool ACC>
 __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
@@ -718,6 +727,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   // loads are unconditional, from clamped addresses (halo rule and unused values applied at the
   // use), so that no join waits for a load in flight
   T p0, p1, fe0, fe1, fe2, frh, fs;
+  double fy = 0.0;
+  const double* __restrict__ yp = ACC ? a.acc64 + base : nullptr;
+  const unsigned b64 = unsigned(clampi(col, 0, n - 1)) * 8u;
   const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
   const T rsg = a.rhs_sign;
   const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
@@ -738,6 +750,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     fe2 = at(E2g + co, bc);
     frh = at(rhsp + co, bc);
     fs = at(sigg + co, bc);
+    if (ACC) fy = at(yp + co, b64);
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg);
@@ -754,6 +767,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       prow[lane] = v0;
       prow[hidx] = lane < 2 * P ? v1 : v0;   // other lanes rewrite their own value
       const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+      const double y64 = fy;
       load_row(r + 1);   // past the last row this reloads a clamped row, unused
       __syncthreads();
       // A: Psi of row r - P
@@ -850,13 +864,16 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         if (p1mom) q += mu * e1 + nu * e2;
         if (has_rhs) q = __builtin_fma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
+        if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
         if (a.mode == 0) {
           const T val = a.sign * rho;
           if (a.out) at(a.out + ro, bo) = val;
           if (a.out_f) at(a.out_f + ro, bof) = float(val);
           acc += double(val) * double(val);
         } else {
-          at(a.out + ro, bo) = psc + qdiv(rho, diag + a.beta * sig);
+          const T un = psc + qdiv(rho, diag + a.beta * sig);
+          at(a.out + ro, bo) = un;
+          if (ACC) at(a.acc64 + ro, unsigned(col) * 8u) = y64 + (double(un) - double(float(y64)));
         }
       }
       __syncthreads();   // the next step overwrites ring slots read above
@@ -1382,6 +1399,8 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
   a.mode = o.mode;
   a.sign = o.sign;
   a.strip_h = o.strip_h;
+  a.psi_f = o.psi_f;
+  a.acc64 = o.acc64;
   return a;
 }
 
@@ -1430,13 +1449,17 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
     a.ntx = (n + ow - 1) / ow;
     const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
     if (o.npartial) *o.npartial = int(grid.x * grid.y * grid.z);
+    if (a.acc64 && a.mode != 1) return hipErrorInvalidValue;
+#define CTF_FUSED(PP, A) hipLaunchKernelGGL((k_pg_fused<PP, T, A>), grid, dim3(kStripW), 0, s, a)
+    const bool acc = a.acc64 != nullptr;
     switch (p) {
-      case 1: hipLaunchKernelGGL((k_pg_fused<1, T>), grid, dim3(kStripW), 0, s, a); break;
-      case 2: hipLaunchKernelGGL((k_pg_fused<2, T>), grid, dim3(kStripW), 0, s, a); break;
-      case 3: hipLaunchKernelGGL((k_pg_fused<3, T>), grid, dim3(kStripW), 0, s, a); break;
-      case 4: hipLaunchKernelGGL((k_pg_fused<4, T>), grid, dim3(kStripW), 0, s, a); break;
+      case 1: if (acc) CTF_FUSED(1, true); else CTF_FUSED(1, false); break;
+      case 2: if (acc) CTF_FUSED(2, true); else CTF_FUSED(2, false); break;
+      case 3: if (acc) CTF_FUSED(3, true); else CTF_FUSED(3, false); break;
+      case 4: if (acc) CTF_FUSED(4, true); else CTF_FUSED(4, false); break;
       default: return hipErrorInvalidValue;
     }
+#undef CTF_FUSED
     return hipGetLastError();
   }
   if (!o.kx_in) {
