@@ -42,6 +42,8 @@ def algorithmic_cost(kernel, p, fused=False):
     kdiff = 16 * W + 34                 # Psi_x, Psi_y (x + y passes), R (x + y passes), k_x, k_y
     if kernel == "pg32":               # refinement inner cycles, full-approximation form
         return (12, stream + kdiff) if fused else (20, stream)   # read x, rhs (+ k_x, k_y); write out
+    if kernel == "pg32_update":        # the same, plus psi64 += u - fl32(psi64): read and write psi64
+        return (28, stream + kdiff + 3) if fused else (36, stream + 3)
     if kernel == "pgk32":              # read x; write k_x, k_y
         return 12, kdiff
     if kernel == "pg64":               # outer residual: read psi (+ k_x, k_y); write float32 residual
@@ -65,7 +67,10 @@ def kernel_symbol(kernel, p, fused):
             "pgk32": "k_pg_diffusivity", "pgk64": "k_pg_diffusivity"}.get(kernel)
     if name is None:
         return kernel, kernel
-    return "%s<%d, %s>" % (name, p, t), "%s_p%d_%s" % (name, p, "f64" if t == "double" else "f32")
+    # the fused kernel's last template argument selects the form with the float64 update (its own
+    # timer class); the stored-diffusivity kernel's second one the residual estimate (mixed mass)
+    args = {"k_pg_fused": "%d, %s, false", "k_pg_diffusivity": "%d, 0, %s"}.get(name, "%d, %s") % (p, t)
+    return "%s<%s>" % (name, args), "%s_p%d_%s" % (name, p, "f64" if t == "double" else "f32")
 
 
 def read_traffic(kernel_symbol):

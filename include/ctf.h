@@ -318,6 +318,8 @@ enum {
   CTF_T_PGK64,         /* stored non-linear PG diffusivities (their own pass), float64 */
   CTF_T_PGK32,         /* same, float32 */
   CTF_T_CSCAT,         /* moments + emission of the corrections (coupled_scatter) */
+  CTF_T_PG32U,         /* the last float32 PG sweep of a refinement step, which also applies the
+                          float64 full-approximation update */
   CTF_T_COUNT
 };
 int ctf_timing_enable(ctf_problem* prob, int on, int capacity, unsigned class_mask);

@@ -570,7 +570,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   o.mode = mode;
   o.sign = sign;
   o.strip_h = P->strip_h;
-  return run_pg<float>(P, CTF_T_PG32, CTF_T_PGK32, P->lf(0), P->st_f, o);
+  return run_pg<float>(P, acc64 ? CTF_T_PG32U : CTF_T_PG32, CTF_T_PGK32, P->lf(0), P->st_f, o);
 }
 
 // one float32 sawtooth cycle on P->e_f; e_is_zero: the correction form's first cycle (e = 0);

@@ -30,7 +30,8 @@ EXPORTED = [
     "ctf_solve_batch", "ctf_set_launch_shape", "ctf_get_launch_shape", "ctf_autotune",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
-                 "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32", "corr_scatter"]
+                 "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32", "corr_scatter",
+                 "pg32_update"]
 
 
 class Config(ctypes.Structure):
