@@ -98,3 +98,21 @@ def test_mixed_precision_downscaled_mixed_workload():
     info = gp.solve(pd, 1e-10, 300)
     assert info["converged"]
     assert rel_w(to_host(pd), psi_o, op.quad, op.h) < 1e-8
+
+
+@pytest.mark.parametrize("n_pg", [0, 1, 2, 3])
+def test_full_approximation_step_follows_the_fp64_cycle(n_pg):
+    """A refinement step with one float32 cycle in full-approximation form is the float64 sawtooth
+    cycle up to float32 rounding (optically thick cells, where the cycle contracts).  n_pg = 0
+    takes the separate update pass; otherwise the last finest sweep applies psi64 += u - fl32(psi64),
+    and odd counts end in the other buffer.  An error in that bookkeeping (a lost or doubled
+    update, a stale float copy of psi) moves the iterate by far more than the bound."""
+    ctf = _ctf()
+    w = workload(N=32, na=2, p=2, L=32.0, patch=4, source="box_center8", seed=0)
+    op, gp = make_pair(w, "pg", "vac", precision=ctf.FP32_IR, n_inner=1, n_pg=n_pg)
+    psi = np.zeros(op.shape())
+    pd = to_dev(psi)
+    for c in range(3):
+        psi = omg.sawtooth_cycle(op, psi)
+        gp.mg_cycle(pd)
+        assert rel_w(to_host(pd), psi, op.quad, op.h) < 1e-4, c

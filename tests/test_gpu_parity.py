@@ -112,7 +112,7 @@ def test_upwind_smoothing_on_a_level(level):
     op, gp = make_pair(w, "pg", "mixed")
     x = random_field(op.shape(level), seed=50 + level)
     s = random_field(op.shape(level), seed=60 + level)
-    for nsw in (1, 3):
+    for nsw in (1, 2, 3, 4):   # single sweeps, pairs in one pass, a pair and a single, two pairs
         xd = to_dev(x)
         gp.smooth(level, ctf.SMOOTH_UPWIND, xd, to_dev(s), nsw)
         ref = omg.upwind_jacobi(op, level, x, s, nsw)
@@ -148,6 +148,18 @@ def test_mg_cycle_iterates(disc, wk, bc):
         psi = omg.sawtooth_cycle(op, psi)
         rel_g = gp.mg_cycle(pd, want_residual=True)
         assert abs(rel_g - rel_o) <= 1e-12 * rel_o
+        assert rel_w(to_host(pd), psi, op.quad, op.h) < 1e-12, c
+
+
+@pytest.mark.parametrize("n_jacobi", [1, 3])
+def test_mg_cycle_iterates_odd_sweep_counts(n_jacobi):
+    """Odd numbers of correction sweeps per level (pairs run as one pass, the last one alone)."""
+    op, gp = make_pair(workload(N=40, na=4, G=2, scatter="downscatter"), "upwind", "mixed", n_jacobi=n_jacobi)
+    psi = np.zeros(op.shape())
+    pd = to_dev(psi)
+    for c in range(3):
+        psi = omg.sawtooth_cycle(op, psi)
+        gp.mg_cycle(pd)
         assert rel_w(to_host(pd), psi, op.quad, op.h) < 1e-12, c
 
 
