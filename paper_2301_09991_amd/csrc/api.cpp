@@ -865,6 +865,9 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   P->pp.bc_vac = P->bc_vac;
   P->pp.isotropic = cfg->pg_isotropic;
   P->pp.r_estimate = cfg->discretisation == CTF_UPWIND ? 0 : cfg->pg_r_estimate;
+  // default launch shape: the single-pass PG form up to p = 2, the stored-diffusivity form above
+  // (fewer registers per wave; measured faster at p = 3 in both precisions)
+  P->pg_fused = cfg->p >= 3 ? 0 : 1;
 
   hipStream_t s = P->stream;
   auto bail = [&](int code) {

@@ -337,7 +337,8 @@ __device__ __forceinline__ T yrot(const T (&w)[W], const T* c, int t) {
 // Residual with given diffusivities (k_x, k_y read with a copied halo):
 //   rho = rhs_sign rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
 //   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
-template <int P, typename T>
+// ACC: a.acc64 is given (mode 1), its values are prefetched with the other per-cell data.
+template <int P, typename T, bool ACC>
 __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
   constexpr int W = 2 * P + 1;
@@ -379,6 +380,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   // applied at the use: a load under a branch would make the wave wait for it at the join.
   T p0, k0, q0, p1, k1, q1;
   T fe0, fe1, fe2, frh, fs;   // emission moments, rhs, sigma_t of output row r - P
+  double fy = 0.0;             // acc64 of output row r - P (ACC)
+  const double* __restrict__ yp = ACC ? a.acc64 + base : nullptr;
+  const unsigned b64 = unsigned(min(gi, n - 1)) * 8u;
   const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
   const T rsg = a.rhs_sign;
   const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
@@ -403,6 +407,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
     fe2 = at(E2g + co, bc);
     frh = at(rhsp + co, bc);
     fs = at(sigg + co, bc);
+    if (ACC) fy = at(yp + co, b64);
   };
   const int rbeg = y0 - P, rend = yend + P;
   load_row(rbeg);
@@ -425,6 +430,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
         rq[kStripW + lane] = q1;
       }
       const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+      const double y64 = fy;
       load_row(r + 1);   // past the last row this reloads a clamped row, unused
       __syncthreads();
       T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
@@ -467,10 +473,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
         } else {
           const T un = pc + qdiv(rho, diag + a.beta * sig);
           at(a.out + ro, bo) = un;
-          if (a.acc64) {
-            double& y = at(a.acc64 + ro, unsigned(gi) * 8u);
-            y = y + (double(un) - double(float(y)));
-          }
+          if (ACC) at(a.acc64 + ro, unsigned(gi) * 8u) = y64 + (double(un) - double(float(y64)));
         }
       }
       ring = ring + 1 == D ? 0 : ring + 1;
@@ -1478,13 +1481,17 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   a.ntx = (n + kStripW - 1) / kStripW;
   const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
   if (o.npartial) *o.npartial = int(grid.x * grid.y * grid.z);
+  if (a.acc64 && a.mode != 1) return hipErrorInvalidValue;
+#define CTF_STREAM(PP, A) hipLaunchKernelGGL((k_pg_stream<PP, T, A>), grid, dim3(kStripW), 0, s, a)
+  const bool acc = a.acc64 != nullptr;
   switch (p) {
-    case 1: hipLaunchKernelGGL((k_pg_stream<1, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_pg_stream<2, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_pg_stream<3, T>), grid, dim3(kStripW), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_pg_stream<4, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 1: if (acc) CTF_STREAM(1, true); else CTF_STREAM(1, false); break;
+    case 2: if (acc) CTF_STREAM(2, true); else CTF_STREAM(2, false); break;
+    case 3: if (acc) CTF_STREAM(3, true); else CTF_STREAM(3, false); break;
+    case 4: if (acc) CTF_STREAM(4, true); else CTF_STREAM(4, false); break;
     default: return hipErrorInvalidValue;
   }
+#undef CTF_STREAM
   return hipGetLastError();
 }
 
