@@ -414,9 +414,9 @@ template <typename T> const T* level_sigma_s(const ctf_problem* P, int l);
 template <> const double* level_sigma_s<double>(const ctf_problem* P, int l) { return P->sigs_d[l]; }
 template <> const float* level_sigma_s<float>(const ctf_problem* P, int l) { return P->sigs_f[l]; }
 
-// n upwind correction sweeps on level l: the first from (xmode, xsrc), result pointer returned;
-// acc != null: the last sweep adds into acc instead of writing a buffer; final != null: the last
-// sweep writes there.  With coupled_scatter every sweep adds the scattering of its input e (the
+// n upwind correction sweeps on level l: the first from (xmode, xsrc), the buffer holding the
+// result returned through result; acc != null: the last sweep adds into acc instead of writing a
+// buffer (result is then not meaningful); final != null: the last sweep writes there.  With coupled_scatter every sweep adds the scattering of its input e (the
 // emission of e on the level, no external source; for the first sweep from the coarser level the
 // moments of UpSamp(e) are those of e on its own level, read at the parent cells).
 template <typename T>

@@ -175,7 +175,7 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
 int wnorm2_partials(const LevelDims& d);
 // out[0] = sum of np partials in a fixed order (a function of np only).  The buffer needs room for
 // sum_partials_extra() more doubles after the np partials (first-stage sums of long inputs).
-hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s,
+hipError_t launch_sum_partials(double* partial, int np, double* out, hipStream_t s,
                                const int* active = nullptr);
 int sum_partials_extra();
 // if *active: rel[0] = sqrt(norm2[0]) / bnorm, *active = (rel > rtol), and steps[0] += 1 while

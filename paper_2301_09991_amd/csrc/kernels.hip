@@ -1596,10 +1596,10 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
 
 int sum_partials_extra() { return kSumBlocks; }
 
-hipError_t launch_sum_partials(const double* partial, int np, double* out, hipStream_t s, const int* active) {
+hipError_t launch_sum_partials(double* partial, int np, double* out, hipStream_t s, const int* active) {
   if (np > 16 * kBlock) {
     // two stages: kSumBlocks chunk sums after the np partials, then their sum
-    double* stage = const_cast<double*>(partial) + np;
+    double* stage = partial + np;
     hipLaunchKernelGGL(k_sum_chunks, dim3(kSumBlocks), dim3(kBlock), 0, s, partial, np, stage, active);
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, stage, kSumBlocks, out, active);
   } else {
