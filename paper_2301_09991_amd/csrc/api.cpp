@@ -37,7 +37,7 @@ bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int validate(const ctf_config* c) {
   if (!c) return fail(CTF_EINVAL, "null config");
-  if (c->n < 2) return fail(CTF_EINVAL, "n must be >= 2");
+  if (c->n < 2 || c->n > 32768) return fail(CTF_EINVAL, "n must be in [2, 32768]");
   if (!(c->length > 0.0)) return fail(CTF_EINVAL, "length must be > 0");
   if (c->discretisation != CTF_UPWIND && (c->p < 1 || c->p > kMaxP))
     return fail(CTF_EINVAL, "p must be 1..4");

@@ -394,14 +394,14 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   const unsigned bc = unsigned(min(gi, n - 1)) * sizeof(T);
   const unsigned bo = unsigned(gi) * sizeof(T), bof = unsigned(gi) * sizeof(float);
   auto load_row = [&](int r) {
-    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n);   // 32-bit in-plane offsets
     p0 = at(psi + ro, b0);
     k0 = at(kxin + ro, b0);
     q0 = at(kyin + ro, b0);
     p1 = at(psi + ro, b1);
     k1 = at(kxin + ro, b1);
     q1 = at(kyin + ro, b1);
-    const size_t co = size_t(clampi(r - P, y0, yend - 1)) * n;   // rows of this strip only
+    const unsigned co = unsigned(clampi(r - P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
     fe0 = at(Eg + co, bc);
     fe1 = at(E1g + co, bc);
     fe2 = at(E2g + co, bc);
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
   const unsigned bo = unsigned(gi) * sizeof(T), bof = unsigned(gi) * sizeof(float);
   auto load_row = [&](int r) {
-    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n);   // 32-bit in-plane offsets
     p0 = at(psi + ro, b0);
     p1 = at(psi + ro, b1);
   };
@@ -743,11 +743,12 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
   const unsigned bc = unsigned(clampi(col, 0, n - 1)) * sizeof(T);
   const unsigned bo = unsigned(col) * sizeof(T), bof = unsigned(col) * sizeof(float);
+  // in-plane element offsets are 32-bit (n < 65536): row offsets cost one scalar multiply
   auto load_row = [&](int r) {
-    const size_t ro = size_t(clampi(r, 0, n - 1)) * n;
+    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n);
     p0 = at(psi + ro, b0);
     p1 = at(psi + ro, b1);
-    const size_t co = size_t(clampi(r - 4 * P, y0, yend - 1)) * n;   // rows of this strip only
+    const unsigned co = unsigned(clampi(r - 4 * P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
     fe0 = at(Eg + co, bc);
     fe1 = at(E1g + co, bc);
     fe2 = at(E2g + co, bc);

@@ -55,6 +55,8 @@ def test_config_validation():
     with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(n=1))
     with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(n=32770))
+    with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(n_jacobi=0))
     with pytest.raises(ctf.CtfError):
         ctf.convfem_stencils(0)
