@@ -758,8 +758,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg);
-  // ring slots of psi row r, Psi row r - P and k row r - 2P, advanced every step
-  int sp = ring_slot(rbeg, PR), sg = ring_slot(rbeg - P, GR), sk = ring_slot(rbeg - 2 * P, KR);
+  // ring slots of psi row r and Psi row r - P, advanced every step.  The k ring is as deep as the unrolled step count (KR = W) and numbered from this strip's first
+  // row, so the k row formed at step t of an unrolled pass sits in slot t: every k slot is static.
+  static_assert(KR == W, "k ring depth equals the unroll");
+  int sp = ring_slot(rbeg, PR), sg = ring_slot(rbeg - P, GR);
   for (int r0 = rbeg; r0 < rend; r0 += W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
@@ -807,8 +809,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
           const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
           const T rx = ar * mu * (yrot(wMx, cm, t) - px);
           const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-          T* const k0r = &s_k[sk][0][P];
-          T* const k1r = &s_k[sk][1][P];
+          T* const k0r = &s_k[t][0][P];
+          T* const k1r = &s_k[t][1][P];
           if (a.iso) {
             const T kk = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
             k0r[lane] = kk;
@@ -832,7 +834,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       {
         const int srow = r - 3 * P;
         const T* const spr = s_psi[ring_back(sp, 3 * P, PR)];
-        const int ks = (srow >= 0 && srow < n) ? ring_back(sk, P, KR) : ring_slot(clampi(srow, 0, n - 1), KR);
+        // k of row srow (formed P steps ago), or of the nearest interior row (formed at step row + 2P)
+        int ks = (t + W - P) % W;
+        if (srow < 0 || srow >= n) ks = int(unsigned(clampi(srow, 0, n - 1) + 2 * P - rbeg) % unsigned(W));
         const T* const kxr = &s_k[ks][0][P];
         const T* const kyr = &s_k[ks][1][P];
         T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0;
@@ -857,7 +861,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       // D: output row r - 4P
       const int o = r - 4 * P;
       if (o >= y0 && writer) {
-        const int gs = ring_back(sg, 3 * P, GR), ks = ring_back(sk, 2 * P, KR);
+        const int gs = ring_back(sg, 3 * P, GR), ks = (t + W - 2 * P) % W;
         const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
         const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
         const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
@@ -883,7 +887,6 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       __syncthreads();   // the next step overwrites ring slots read above
       sp = ring_next(sp, PR);
       sg = ring_next(sg, GR);
-      sk = ring_next(sk, KR);
     }
   }
   if (a.partial) {
