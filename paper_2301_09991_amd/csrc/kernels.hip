@@ -709,6 +709,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     cm[t] = a.st.m[t];
     cd[t] = a.st.d[t];
     ck[t] = a.st.k[t];
+    if constexpr (sizeof(T) == 8 && P <= 2) {
+      // float64 up to p = 2: keep the taps in vector registers (occupancy is bound by LDS there, and
+      // in scalar registers they crowd out the loop's addresses, which then spill into vector lanes)
+      asm volatile("" : "+v"(cm[t]));
+      asm volatile("" : "+v"(cd[t]));
+      asm volatile("" : "+v"(ck[t]));
+    }
   }
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
   T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
