@@ -264,7 +264,7 @@ int ctf_norm(ctf_problem* prob, const double* v, double* out);
  * correction, psi (or the float32 correction) gains s * net / (4 pi) in every ordinate,
  * interpolated bilinearly from the cell centres of that level to the finest cell centres, after the
  * finest correction sweeps and before the finest smoothing.  In
- * ctf_solve plain multigrid stays the judge: a step with the correction that multiplies the
+ * ctf_solve plain multigrid stays the arbiter: a step with the correction that multiplies the
  * residual by more than cnn_max_growth (or makes it non-finite) is undone and the correction is
  * switched off for the rest of the solve; at most cnn_max_uses steps apply it (in a float32
  * refinement step, only its first cycle).

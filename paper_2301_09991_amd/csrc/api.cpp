@@ -1149,7 +1149,7 @@ int ctf_solve(ctf_problem* P, double* psi, double rtol, int max_cycles, ctf_solv
         rel = nr / P->bnorm;
       }
     }
-    // plain multigrid is the fallback and the judge: a step with the learned correction that
+    // plain multigrid is the fallback and the arbiter: a step with the learned correction that
     // raised the residual (or made it non-finite) is undone and the correction switched off
     if (last_used_cnn && (rc == CTF_ENONFINITE || (rc == CTF_OK && rel > P->cfg.cnn_max_growth * prev))) {
       CTF_HIP(hipMemcpyAsync(psi, P->cnn_backup, n * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
