@@ -42,7 +42,7 @@ enum {
   CTF_ENOMEM = -2,       /* workspace too small */
   CTF_EHIP = -3,         /* a HIP runtime call failed */
   CTF_ENONFINITE = -4,   /* NaN or Inf found in a residual norm */
-  CTF_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  CTF_EUNSUPPORTED = -5  /* valid request the library does not implement */
 };
 
 /* discretisation */
