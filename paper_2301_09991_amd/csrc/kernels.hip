@@ -918,9 +918,11 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
 // Threads are laid out as in the correction sweep below: 64 columns x row groups of kCorrRows rows,
 // each thread walking its rows in the ordinate's downwind y order with every load issued up front
 // from clamped addresses, so psi is read once for the centre and once, from cache, as x neighbour.
+// A block takes K consecutive ordinates of one face (same signs, so the same walk and upwind
+// column): the per-cell emission and sigma_t of its rows are loaded once for all K.
 constexpr int kCorrRows = 8;
 constexpr int kFullBlock = 256;
-template <typename T>
+template <typename T, int K>
 __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int bc_vac,
                                                             const T* __restrict__ psi,
                                                             const T* __restrict__ E, int nmomE,
@@ -933,66 +935,86 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
   const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
   const int i = tx * 64 + int(threadIdx.x & 63);
   const int jb = (ty * (kFullBlock / 64) + int(threadIdx.x >> 6)) * kCorrRows;
-  const int dir = blockIdx.y, g = blockIdx.z;
+  const int d0 = int(blockIdx.y) * K, g = blockIdx.z;
   const size_t ncell = size_t(n) * n;
-  const size_t plane = (size_t(g) * nd + dir) * ncell;
-  double acc = 0.0;
+  double acc = 0.0;   // sum over the block's ordinates of w_n (sign rho)^2
   if (i < n && jb < n) {
-    const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
+    const T h = T(L.dims.h);
+    const T mu0 = L.mu[d0], nu0 = L.nu[d0];   // signs shared by the K ordinates
     const int je = min(jb + kCorrRows, n);
-    const int iu = mu > T(0) ? i - 1 : i + 1;
+    const int iu = mu0 > T(0) ? i - 1 : i + 1;
     const bool x_in = iu >= 0 && iu < n;
     const int iuc = clampi(iu, 0, n - 1);
-    const bool xvac = mu > T(0) ? (bc_vac & 1) : (bc_vac & 2);
-    const bool yvac = nu > T(0) ? (bc_vac & 4) : (bc_vac & 8);
-    const T amu = tabs(mu) / h, anu = tabs(nu) / h;
+    const bool xvac = mu0 > T(0) ? (bc_vac & 1) : (bc_vac & 2);
+    const bool yvac = nu0 > T(0) ? (bc_vac & 4) : (bc_vac & 8);
     const T* __restrict__ sg = L.sigma_t + size_t(g) * ncell;
-    const T* __restrict__ pp = psi + plane;
     const T* __restrict__ E0 = E + size_t(g) * nmomE * ncell;
-    const T* __restrict__ E1 = nmomE > 1 ? E0 + ncell : E0;
-    const T* __restrict__ E2 = nmomE > 1 ? E0 + 2 * ncell : E0;
-    const T* __restrict__ rp = rhs ? rhs + plane : E0;
-    const bool down = nu > T(0);
+    const bool down = nu0 > T(0);
     const int j0 = down ? jb : je - 1;
     const int ju = down ? j0 - 1 : j0 + 1;
     const bool y_in = ju >= 0 && ju < n;
-    T vc[kCorrRows], vx[kCorrRows], q0[kCorrRows], q1[kCorrRows], q2[kCorrRows], vr[kCorrRows],
-        vs[kCorrRows];
+    const int rows = je - jb;
+    // per-cell values, once for the K ordinates
+    T q0[kCorrRows], q1[kCorrRows], q2[kCorrRows], vs[kCorrRows];
 #pragma unroll
     for (int t = 0; t < kCorrRows; ++t) {
       const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
       const size_t row = size_t(j) * n;
-      vc[t] = pp[row + i];
-      vx[t] = pp[row + iuc];
       q0[t] = E0[row + i];
-      q1[t] = E1[row + i];
-      q2[t] = E2[row + i];
-      vr[t] = rp[row + i];
       vs[t] = sg[row + i];
+      q1[t] = q2[t] = T(0);
     }
-    T prev = pp[size_t(clampi(ju, 0, n - 1)) * n + i];   // the upwind row, used only inside the domain
-    const int rows = je - jb;
+    if (nmomE > 1) {
 #pragma unroll
-    for (int t = 0; t < kCorrRows; ++t) {
-      if (t >= rows) break;
-      const size_t cell = size_t(down ? j0 + t : j0 - t) * n + i;
-      const T pc = vc[t];
-      const T px = x_in ? vx[t] : (xvac ? T(0) : pc);
-      const T py = (t > 0 || y_in) ? prev : (yvac ? T(0) : pc);
-      T q = q0[t];
-      if (nmomE > 1) q += mu * q1[t] + nu * q2[t];
-      if (rhs) q += vr[t];
-      const T sig = vs[t];
-      const T rho = q - amu * (pc - px) - anu * (pc - py) - sig * pc;
-      if (mode == 0) {
-        const T val = sign * rho;
-        if (out) out[plane + cell] = val;
-        if (out_f) out_f[plane + cell] = float(val);
-        acc += double(val) * double(val);
-      } else {
-        out[plane + cell] = pc + rho / (amu + anu + sig);
+      for (int t = 0; t < kCorrRows; ++t) {
+        const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
+        const size_t row = size_t(j) * n;
+        q1[t] = E0[ncell + row + i];
+        q2[t] = E0[2 * ncell + row + i];
       }
-      prev = pc;
+    }
+#pragma unroll 1
+    for (int k = 0; k < K; ++k) {   // not unrolled: one ordinate's rows in registers at a time
+      const int dir = d0 + k;
+      const size_t plane = (size_t(g) * nd + dir) * ncell;
+      const T mu = L.mu[dir], nu = L.nu[dir];
+      const T amu = tabs(mu) / h, anu = tabs(nu) / h;
+      const T* __restrict__ pp = psi + plane;
+      const T* __restrict__ rp = rhs ? rhs + plane : pp;
+      T vc[kCorrRows], vx[kCorrRows], vr[kCorrRows];
+#pragma unroll
+      for (int t = 0; t < kCorrRows; ++t) {
+        const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
+        const size_t row = size_t(j) * n;
+        vc[t] = pp[row + i];
+        vx[t] = pp[row + iuc];
+        vr[t] = rp[row + i];
+      }
+      T prev = pp[size_t(clampi(ju, 0, n - 1)) * n + i];   // the upwind row, used only inside the domain
+      double acck = 0.0;
+#pragma unroll
+      for (int t = 0; t < kCorrRows; ++t) {
+        if (t >= rows) break;
+        const size_t cell = size_t(down ? j0 + t : j0 - t) * n + i;
+        const T pc = vc[t];
+        const T px = x_in ? vx[t] : (xvac ? T(0) : pc);
+        const T py = (t > 0 || y_in) ? prev : (yvac ? T(0) : pc);
+        T q = q0[t];
+        if (nmomE > 1) q += mu * q1[t] + nu * q2[t];
+        if (rhs) q += vr[t];
+        const T sig = vs[t];
+        const T rho = q - amu * (pc - px) - anu * (pc - py) - sig * pc;
+        if (mode == 0) {
+          const T val = sign * rho;
+          if (out) out[plane + cell] = val;
+          if (out_f) out_f[plane + cell] = float(val);
+          acck += double(val) * double(val);
+        } else {
+          out[plane + cell] = pc + rho / (amu + anu + sig);
+        }
+        prev = pc;
+      }
+      acc += double(L.w[dir]) * acck;
     }
   }
   if (partial) {
@@ -1006,7 +1028,7 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
     }
     if (threadIdx.x == 0) {
       const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
-      partial[b] = red[0] * double(L.w[dir]) * L.dims.h * L.dims.h;
+      partial[b] = red[0] * L.dims.h * L.dims.h;
     }
   }
 }
@@ -1524,14 +1546,22 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
                               double* partial, size_t partial_cap, int* npartial) {
   const int n = L.dims.n;
   const int rows_per_block = (kFullBlock / 64) * kCorrRows;
-  const dim3 grid(unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block), L.dims.nd,
-                  L.dims.G);
+  // ordinates per block: four when a face holds a multiple of four (n_dir = 8 or 4 faces of na^2)
+  const int per_face = L.dims.na * L.dims.na;
+  const int kb = per_face % 4 == 0 ? 4 : 1;
+  const dim3 grid(unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block),
+                  unsigned(L.dims.nd / kb), L.dims.G);
   const size_t blocks = size_t(grid.x) * grid.y * grid.z;
   if (partial && blocks > partial_cap) return hipErrorInvalidValue;
   if (mode == 0 && !out && !out_f) return hipErrorInvalidValue;
+  if (L.dims.nd % per_face) return hipErrorInvalidValue;
   if (npartial) *npartial = int(blocks);
-  hipLaunchKernelGGL(k_upwind_full<T>, grid, dim3(kFullBlock), 0, s, L, bc_vac, psi, E, nmomE, out, out_f,
-                     mode, sign, rhs, partial);
+  if (kb == 4)
+    hipLaunchKernelGGL((k_upwind_full<T, 4>), grid, dim3(kFullBlock), 0, s, L, bc_vac, psi, E, nmomE, out, out_f,
+                       mode, sign, rhs, partial);
+  else
+    hipLaunchKernelGGL((k_upwind_full<T, 1>), grid, dim3(kFullBlock), 0, s, L, bc_vac, psi, E, nmomE, out, out_f,
+                       mode, sign, rhs, partial);
   return hipGetLastError();
 }
 
