@@ -46,8 +46,8 @@ def algorithmic_cost(kernel, p, fused=False):
         return (28, stream + kdiff + 3) if fused else (36, stream + 3)
     if kernel == "pgk32":              # read x; write k_x, k_y
         return 12, kdiff
-    if kernel == "pg64":               # outer residual: read psi (+ k_x, k_y); write float32 residual
-        return (12, stream + kdiff) if fused else (28, stream)
+    if kernel == "pg64":               # outer residual: read psi (+ k_x, k_y); write float32 residual and psi
+        return (16, stream + kdiff) if fused else (32, stream)
     if kernel == "pgk64":
         return 24, kdiff
     if kernel in ("corr0", "upwind32"):

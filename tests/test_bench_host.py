@@ -15,6 +15,7 @@ def test_algorithmic_cost_model():
     assert (b, f) == (12, 32 * 5 + 23 + 16 * 5 + 34) == (12, 297)
     assert bench.algorithmic_cost("pg32", 2, fused=False) == (20, 32 * 5 + 23)
     assert bench.algorithmic_cost("pg32_update", 2, fused=True)[0] == 12 + 16   # psi64 read and written
+    assert bench.algorithmic_cost("pg64", 2, fused=True)[0] == 8 + 4 + 4   # psi read; residual and fl32(psi) written
     assert bench.algorithmic_cost("moments", 2) == (4, 6)
     with pytest.raises(KeyError):
         bench.algorithmic_cost("no_such_class", 2)
