@@ -363,6 +363,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
     cm[t] = a.st.m[t];
     cd[t] = a.st.d[t];
     ck[t] = a.st.k[t];
+    if constexpr (sizeof(T) == 8 && P == 3) {
+      // float64 at p = 3: taps in vector registers (two waves per SIMD either way), so the loop's
+      // scalar values do not spill into vector lanes
+      asm volatile("" : "+v"(cm[t]));
+      asm volatile("" : "+v"(cd[t]));
+      asm volatile("" : "+v"(ck[t]));
+    }
   }
   // x-pass results of the last W rows, slot = (row - first row) % W
   T wXd[W] = {}, wXm[W] = {}, wXk[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA2y[W] = {}, wA3y[W] = {};
