@@ -56,3 +56,16 @@ def test_committed_traffic_summary_is_well_formed():
     scaled, alg = float(vals["scaled bytes per launch"]), float(vals["algorithmic bytes per launch"])
     assert alg == 12 * 256 * 256 * 512 * 2
     assert 1.0 <= scaled / alg < 1.5   # measured HBM bytes cannot undercut the arrays the kernel must move
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """bench.py --gpus N with N > 1 exits (status 2) with a message, before touching a GPU."""
+    import json
+    import subprocess
+    import sys
+    root = os.path.dirname(bench.__file__)
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
