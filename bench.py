@@ -67,9 +67,9 @@ def kernel_symbol(kernel, p, fused):
             "pgk32": "k_pg_diffusivity", "pgk64": "k_pg_diffusivity"}.get(kernel)
     if name is None:
         return kernel, kernel
-    # the fused kernel's last template argument selects the form with the float64 update (its own
-    # timer class); the stored-diffusivity kernel's second one the residual estimate (mixed mass)
-    args = {"k_pg_fused": "%d, %s, false", "k_pg_diffusivity": "%d, 0, %s"}.get(name, "%d, %s") % (p, t)
+    # the second template argument of both kernels is the residual estimate (0, the mixed mass); the
+    # fused kernel's last one selects the form with the float64 update (its own timer class)
+    args = {"k_pg_fused": "%d, 0, %s, false", "k_pg_diffusivity": "%d, 0, %s"}.get(name, "%d, %s") % (p, t)
     return "%s<%s>" % (name, args), "%s_p%d_%s" % (name, p, "f64" if t == "double" else "f32")
 
 

@@ -356,7 +356,7 @@ int finest64(ctf_problem* P, const double* psi, double* out, int mode, double si
   if (frozen) {
     o.kx_in = P->kx;
     o.ky_in = P->ky;
-  } else if (k_float || !P->pg_fused || P->pp.r_estimate) {
+  } else if (k_float || !P->pg_fused) {
     o.kx_out = P->kx;
     o.ky_out = P->ky;
     if (k_float) {
@@ -559,7 +559,7 @@ int inner_finest32(ctf_problem* P, const float* x, float* out, int mode, float s
   if (c.discretisation != CTF_CONVFEM_PG) {
     o.kx_in = P->kx_f;   // frozen k
     o.ky_in = P->ky_f;
-  } else if (!P->pg_fused || P->pp.r_estimate) {
+  } else if (!P->pg_fused) {
     o.kx_out = P->kx_f;  // full-approximation form: k of x itself, stored then read
     o.ky_out = P->ky_f;
   }

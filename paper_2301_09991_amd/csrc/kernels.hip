@@ -20,6 +20,8 @@ __device__ __forceinline__ float tabs(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double tabs(double x) { return __builtin_fabs(x); }
 __device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
 __device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float tfma(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double tfma(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // a / b for b > 0: float32 as a times the hardware reciprocal (within 2 ulp; the float32 kernels
 // serve the refinement's inner cycles), float64 exactly rounded.
@@ -39,10 +41,14 @@ __device__ __forceinline__ T& at(T* row, unsigned boff) {
 
 // Anisotropic diffusivity of one direction component (eq. ano-k):
 //   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
+// The diffusivity helpers evaluate exactly as written: contraction is off inside them and the
+// fused multiply-adds are explicit (a contraction left to the compiler depends on the surrounding
+// code), so that every kernel forming k gives the same bits.
 template <typename T>
 __device__ __forceinline__ T pg_k(T mu, T R, T Psi, T h, T akabs, T aksq, T eps) {
+#pragma clang fp contract(off)
   return tmin(tmin(h * tabs(mu), qdiv(akabs * tabs(R) * h, eps + tabs(Psi))),
-              qdiv(aksq * R * R * h, eps + tabs(mu) * Psi * Psi));
+              qdiv(aksq * R * R * h, tfma(tabs(mu) * Psi, Psi, eps)));
 }
 
 // Isotropic diffusivity (the residual-based form with the mixed-mass residual R = R_x + R_y):
@@ -50,13 +56,46 @@ __device__ __forceinline__ T pg_k(T mu, T R, T Psi, T h, T akabs, T aksq, T eps)
 //           aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|)/2 (Psi_x^2 + Psi_y^2))),
 //   q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
 template <typename T>
+__device__ __forceinline__ T dot2(T a, T b, T c, T d) {
+#pragma clang fp contract(off)
+  return tfma(a, b, c * d);
+}
+
+template <typename T>
 __device__ __forceinline__ T pg_k_iso(T mu, T nu, T R, T px, T py, T h, T akabs, T aksq, T eps) {
-  const T s2 = px * px + py * py;
-  const T q = qdiv(mu * px + nu * py, eps + s2);
-  const T kabs = qdiv(akabs * tabs(R) * h, eps + (tabs(px) + tabs(py)) * T(0.5));
-  const T ksq = qdiv(aksq * R * R * h, eps + (tabs(q * px) + tabs(q * py)) * T(0.5) * s2);
+#pragma clang fp contract(off)
+  const T s2 = dot2(px, px, py, py);
+  const T q = qdiv(dot2(mu, px, nu, py), eps + s2);
+  const T kabs = qdiv(akabs * tabs(R) * h, tfma(tabs(px) + tabs(py), T(0.5), eps));
+  const T ksq = qdiv(aksq * R * R * h, tfma((tabs(q * px) + tabs(q * py)) * T(0.5), s2, eps));
   const T hm = h * mu, hn = h * nu;
-  return tmin(tmin(T(sqrt(hm * hm + hn * hn)), kabs), ksq);
+  return tmin(tmin(T(sqrt(dot2(hm, hm, hn, hn))), kabs), ksq);
+}
+
+// Emission of one ordinate from the flux moments: e0 + mu e1 + nu e2 (evaluated as written, so that
+// every kernel gives the same bits)
+template <typename T>
+__device__ __forceinline__ T emission_p1(T e0, T e1, T e2, T mu, T nu) {
+#pragma clang fp contract(off)
+  return e0 + dot2(mu, e1, nu, e2);
+}
+
+// The mixed-mass estimate of the isotropic form, R = R_x + R_y (the two terms rounded as formed)
+template <typename T>
+__device__ __forceinline__ T pg_r_mixed(T rx, T ry) {
+#pragma clang fp contract(off)
+  return rx + ry;
+}
+
+// Residual estimate of the isotropic form from the difference of the advection estimates
+// mu Psi_x + nu Psi_y of degree P (px, py) and of the other degree (qx, qy): RE 1 takes the degree
+// P - 1 (R^Low = degree P minus degree P - 1), RE 2 the degree P + 1 (R^High = degree P + 1 minus
+// degree P).
+template <int RE, typename T>
+__device__ __forceinline__ T pg_r_other_degree(T mu, T nu, T px, T py, T qx, T qy) {
+#pragma clang fp contract(off)
+  const T adv = dot2(mu, px, nu, py), advq = dot2(mu, qx, nu, qy);
+  return RE == 1 ? adv - advq : advq - adv;
 }
 
 __device__ __forceinline__ int parent_dir_dev(int n, int na) {
@@ -468,8 +507,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
         const T dy = kyc * yrot(wXm, ck, t) + yrot(wA2y, ck, t) - pc * yrot(wA3y, ck, t);
         const size_t ro = base + size_t(o) * n;
         T q = e0;
-        if (p1mom) q += mu * e1 + nu * e2;
-        if (has_rhs) q = __builtin_fma(rsg, rh, q);
+        if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
+        if (has_rhs) q = tfma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * pc;
         if (a.psi_f) at(a.psi_f + ro, bof) = float(pc);
         if (a.mode == 0) {
@@ -636,14 +675,12 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
             qx += cmq[v] * wQd[v];
             qy += cdq[v] * wQm[v];
           }
-          const T adv = mu * px + nu * py, advq = mu * qx + nu * qy;
-          const T R = RE == 1 ? adv - advq : advq - adv;
-          kx = ky = pg_k_iso(mu, nu, R, px, py, h, akabs, aksq, eps);
+          kx = ky = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, h, akabs, aksq, eps);
         } else {
           const T rx = ar * mu * (yrot(wMx, cm, t) - px);
           const T ry = ar * nu * (yrot(wMy, cm, t) - py);
           if (a.iso) {
-            kx = ky = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+            kx = ky = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, h, akabs, aksq, eps);
           } else {
             kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
             ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
@@ -683,10 +720,17 @@ __device__ __forceinline__ int ring_back(int s, int off, int depth) { return s >
 __device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == depth ? 0 : s + 1; }
 
 // ACC: a.acc64 is given (mode 1), its values are prefetched with the other per-cell data.
-template <int P, typename T, bool ACC>
+// RE: residual estimate of the isotropic form, as in k_pg_diffusivity (0 the mixed mass; 1 / 2 the
+// advection estimates of degrees P and P - 1 / P + 1, the other degree x-passed in stage A into
+// shifted windows that reach back to row r - 2P - Q when stage B forms k of row r - 2P).
+template <int P, int RE, typename T, bool ACC>
 __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
+  static_assert(RE == 0 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP), "residual estimate degree");
   constexpr int W = 2 * P + 1;
+  constexpr int PQ = RE == 1 ? P - 1 : (RE == 2 ? P + 1 : 0);   // the other degree
+  constexpr int WQ = 2 * PQ + 1;
+  constexpr int KQ = RE ? 2 * P + PQ + 1 : 1;
   constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
   constexpr int PR = 4 * P + 1;         // psi rows kept (r - 4P .. r)
   constexpr int GR = 3 * P + 1;         // Psi rows kept (r - 4P .. r - P)
@@ -724,8 +768,18 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       asm volatile("" : "+v"(ck[t]));
     }
   }
+  T cmq[WQ] = {}, cdq[WQ] = {};
+  if constexpr (RE != 0) {
+#pragma unroll
+    for (int t = 0; t < WQ; ++t) {
+      cmq[t] = a.st.mr[t];
+      cdq[t] = a.st.dr[t];
+    }
+  }
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
   T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
+  // shifted windows (newest row last) of the other degree's x-passes
+  T wQd[KQ] = {}, wQm[KQ] = {};
   // psi row loads: lane l -> column c0 - P + l; lanes < 2P also column c0 - P + 64 + l
   const int lc0 = c0 - P + lane, lc1 = lc0 + kStripW;
   const int cc0 = clampi(lc0, 0, n - 1), cc1 = clampi(lc1, 0, n - 1);
@@ -805,31 +859,61 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         wXm[t] = xm;
         gxr[lane] = yrot(wXd, cm, t);
         gyr[lane] = yrot(wXm, cd, t);
+        if constexpr (RE != 0) {
+          // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row; lq = lane on every lane
+          // whose k is read (P .. 63 - P)
+          const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
+          T qd = 0, qm = 0;
+#pragma unroll
+          for (int u = 0; u < WQ; ++u) {
+            const T v = prow[lq + P - PQ + u];
+            qd += cdq[u] * v;
+            qm += cmq[u] * v;
+          }
+          push(wQd, qd);
+          push(wQm, qm);
+        }
       }
-      __syncthreads();
+      // the other-degree estimates read Psi of their own lane only: no wait for its neighbours
+      if constexpr (RE == 0) __syncthreads();
       // B: k of row r - 2P
       {
-        T mx = 0, my = 0;
+        if constexpr (RE == 0) {
+          T mx = 0, my = 0;
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-          mx += cm[u] * gxr[lane - P + u];
-          my += cm[u] * gyr[lane - P + u];
+          for (int u = 0; u < W; ++u) {
+            mx += cm[u] * gxr[lane - P + u];
+            my += cm[u] * gyr[lane - P + u];
+          }
+          wMx[t] = mx;
+          wMy[t] = my;
         }
-        wMx[t] = mx;
-        wMy[t] = my;
         const int rk = r - 2 * P;
         if (rk >= 0 && rk < n) {
           const int gs = ring_back(sg, P, GR);
           const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
-          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
-          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
           T* const k0r = &s_k[t][0][P];
           T* const k1r = &s_k[t][1][P];
-          if (a.iso) {
-            const T kk = pg_k_iso(mu, nu, rx + ry, px, py, h, akabs, aksq, eps);
+          if constexpr (RE != 0) {
+            // Psi of the other degree on row rk: y-pass over the window rows rk - Q .. rk + Q
+            T qx = 0, qy = 0;
+#pragma unroll
+            for (int v = 0; v < WQ; ++v) {
+              qx += cmq[v] * wQd[v];
+              qy += cdq[v] * wQm[v];
+            }
+            const T kk = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, h, akabs, aksq, eps);
+            k0r[lane] = kk;
+            k1r[lane] = kk;
+          } else if (a.iso) {
+            const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+            const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+            const T kk = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, h, akabs, aksq, eps);
             k0r[lane] = kk;
             k1r[lane] = kk;
           } else {
+            const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+            const T ry = ar * nu * (yrot(wMy, cm, t) - py);
             k0r[lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
             k1r[lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
           }
@@ -883,8 +967,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         const T dy = kyc * yrot(wA1y, ck, t) + yrot(wA2y, ck, t) - psc * yrot(wA3y, ck, t);
         const size_t ro = base + size_t(o) * n;
         T q = e0;
-        if (p1mom) q += mu * e1 + nu * e2;
-        if (has_rhs) q = __builtin_fma(rsg, rh, q);
+        if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
+        if (has_rhs) q = tfma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
         if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
         if (a.mode == 0) {
@@ -1007,7 +1091,7 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
         const T px = x_in ? vx[t] : (xvac ? T(0) : pc);
         const T py = (t > 0 || y_in) ? prev : (yvac ? T(0) : pc);
         T q = q0[t];
-        if (nmomE > 1) q += mu * q1[t] + nu * q2[t];
+        if (nmomE > 1) q = emission_p1(q, q1[t], q2[t], mu, nu);
         if (rhs) q += vr[t];
         const T sig = vs[t];
         const T rho = q - amu * (pc - px) - anu * (pc - py) - sig * pc;
@@ -1499,8 +1583,8 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
-    // fused: the diffusivities of psi are formed on the fly (mixed-mass estimate only)
-    if (pp.r_estimate) return hipErrorInvalidValue;
+    // fused: the diffusivities of psi are formed on the fly
+    if (pp.r_estimate && !pp.isotropic) return hipErrorInvalidValue;
     a.out = o.out;
     a.out_f = o.out_f;
     a.partial = o.partial;
@@ -1509,13 +1593,21 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
     const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
     if (o.npartial) *o.npartial = int(grid.x * grid.y * grid.z);
     if (a.acc64 && a.mode != 1) return hipErrorInvalidValue;
-#define CTF_FUSED(PP, A) hipLaunchKernelGGL((k_pg_fused<PP, T, A>), grid, dim3(kStripW), 0, s, a)
+#define CTF_FUSED(PP, RE) \
+  if (acc) hipLaunchKernelGGL((k_pg_fused<PP, RE, T, true>), grid, dim3(kStripW), 0, s, a); \
+  else hipLaunchKernelGGL((k_pg_fused<PP, RE, T, false>), grid, dim3(kStripW), 0, s, a)
     const bool acc = a.acc64 != nullptr;
-    switch (p) {
-      case 1: if (acc) CTF_FUSED(1, true); else CTF_FUSED(1, false); break;
-      case 2: if (acc) CTF_FUSED(2, true); else CTF_FUSED(2, false); break;
-      case 3: if (acc) CTF_FUSED(3, true); else CTF_FUSED(3, false); break;
-      case 4: if (acc) CTF_FUSED(4, true); else CTF_FUSED(4, false); break;
+    switch (p * 4 + pp.r_estimate) {
+      case 4: CTF_FUSED(1, 0); break;
+      case 8: CTF_FUSED(2, 0); break;
+      case 12: CTF_FUSED(3, 0); break;
+      case 16: CTF_FUSED(4, 0); break;
+      case 9: CTF_FUSED(2, 1); break;
+      case 13: CTF_FUSED(3, 1); break;
+      case 17: CTF_FUSED(4, 1); break;
+      case 6: CTF_FUSED(1, 2); break;
+      case 10: CTF_FUSED(2, 2); break;
+      case 14: CTF_FUSED(3, 2); break;
       default: return hipErrorInvalidValue;
     }
 #undef CTF_FUSED

@@ -22,8 +22,8 @@ def test_algorithmic_cost_model():
 
 
 def test_kernel_symbols_match_the_profiler_names():
-    assert bench.kernel_symbol("pg32", 2, True) == ("k_pg_fused<2, float, false>", "k_pg_fused_p2_f32")
-    assert bench.kernel_symbol("pg64", 3, True) == ("k_pg_fused<3, double, false>", "k_pg_fused_p3_f64")
+    assert bench.kernel_symbol("pg32", 2, True) == ("k_pg_fused<2, 0, float, false>", "k_pg_fused_p2_f32")
+    assert bench.kernel_symbol("pg64", 3, True) == ("k_pg_fused<3, 0, double, false>", "k_pg_fused_p3_f64")
     assert bench.kernel_symbol("pg32", 2, False) == ("k_pg_stream<2, float>", "k_pg_stream_p2_f32")
     assert bench.kernel_symbol("pgk64", 3, False) == ("k_pg_diffusivity<3, 0, double>", "k_pg_diffusivity_p3_f64")
     assert bench.kernel_symbol("corr0", 2, True) == ("corr0", "corr0")
@@ -52,7 +52,7 @@ def test_committed_traffic_summary_is_well_formed():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    assert vals["kernel"] == "k_pg_fused<2, float, false>"
+    assert vals["kernel"] == "k_pg_fused<2, 0, float, false>"
     scaled, alg = float(vals["scaled bytes per launch"]), float(vals["algorithmic bytes per launch"])
     assert alg == 12 * 256 * 256 * 512 * 2
     assert 1.0 <= scaled / alg < 1.5   # measured HBM bytes cannot undercut the arrays the kernel must move

@@ -49,7 +49,7 @@ def test_estimate_operator(case, bc):
     out = gp.empty()
     gp.apply_operator(to_dev(psi), out, ctf.OP_RESIDUAL)
     assert _maxrel(to_host(out), omg.finest_residual(op, psi)) < 1e-12
-    # the fused launch shape does not apply to these estimates: both shapes run the two-pass form
+    # the fused and the two-pass kernels give the same bits
     outs = []
     for shape in ((128, 256, 1), (32, 256, 0)):
         gp.set_launch_shape(*shape)
