@@ -101,9 +101,9 @@ typedef struct ctf_config {
                             degree p - 1 (needs p >= 2);
                             CTF_R_HIGH: R = the same with the filters of degree p + 1 minus
                             (mu Psi_x + nu Psi_y) (needs p <= 3).  No factor on the low and high
-                            forms.  Other than CTF_R_MIXED_MASS needs pg_isotropic = 1; their
-                            diffusivities are formed in a pass of their own and stored (the fused
-                            launch shape does not apply).  Default CTF_R_MIXED_MASS. */
+                            forms.  Other than CTF_R_MIXED_MASS needs pg_isotropic = 1.  Every
+                            estimate runs in either launch shape (pg_fused), with the same bits.
+                            Default CTF_R_MIXED_MASS. */
 } ctf_config;
 
 typedef struct ctf_problem ctf_problem;
