@@ -327,3 +327,55 @@ def test_low_high_estimates_vanish_on_linear_fields():
     Rh, _, _ = isotropic_residual_estimate(psi, quad, h, h, 2, VAC, r_estimate="high")
     assert np.abs(Rl).max() > 1e-3 and np.abs(Rh).max() > 1e-3
     assert np.abs(Rl - Rh).max() > 1e-3
+
+
+@pytest.mark.parametrize("axis", ["x", "y"])
+def test_anisotropic_pg_diffusivity_cubic_closed_form(axis):
+    """Eq. ano-k on psi = x^3 (or y^3) with the linear filters and dx != dy, every quantity in
+    closed form.  Along the field's axis (spacing a, direction cosine c = mu or nu):
+    Psi = ((s+a)^3 - (s-a)^3) / 2a = 3s^2 + a^2 (the mass along the other axis acts on a constant),
+    the mass filter [1/6, 2/3, 1/6] maps it to 3s^2 + 2a^2, so R = alpha_r c a^2 with alpha_r = 3;
+    k = min(a |c|, akabs |R| a / (eps + |Psi|), aksq R^2 a / (eps + |c| Psi^2)), akabs = 1/8,
+    aksq = 1.  Across the field Psi = R = 0, so k = 0 there.  On this grid k_abs is the minimum near
+    the low edge and k_square further out, so swapping the two constants, taking the other axis'
+    spacing, or dropping |c| from the k_square denominator all change the result."""
+    quad = qd.quadrature(2)
+    mu, nu = quad["mu"][:, None], quad["nu"][:, None]
+    N, dx, dy, eps = 12, 0.3, 0.2, 1e-3
+    a, c = (dx, mu) if axis == "x" else (dy, nu)
+    s = (np.arange(N) + 0.5) * a
+    shape = (1, 1, 1, N) if axis == "x" else (1, 1, N, 1)
+    psi = np.broadcast_to((s ** 3).reshape(shape), (1, 32, N, N)).copy()
+    kx, ky = pg_diffusivity(psi, quad, dx, dy, 1, ZG)
+    si = s[2:-2][None, :]
+    P = 3 * si ** 2 + a ** 2
+    R = 3.0 * c * a ** 2
+    k_abs = (2.0 / 16.0) * np.abs(R) * a / (eps + P)
+    k_sq = (2.0 / 2.0) * R ** 2 * a / (eps + np.abs(c) * P ** 2)
+    ref = np.minimum(np.minimum(a * np.abs(c), k_abs), k_sq)
+    assert (k_abs < k_sq).any() and (k_sq < k_abs).any()     # both bounds are active somewhere
+    along, across = (kx, ky) if axis == "x" else (ky, kx)
+    got = along[0, :, 2:-2, 2:-2] if axis == "x" else np.swapaxes(along[0, :, 2:-2, 2:-2], 1, 2)
+    assert np.allclose(got, ref[:, None, :], rtol=1e-10, atol=1e-16)
+    assert np.abs(across).max() < 1e-20      # rounding only: Psi and R vanish across the field
+
+
+@pytest.mark.parametrize("na,ref", [(4, 0.978), (8, 0.994), (16, 0.9986)])
+def test_p1_emission_scale(na, ref):
+    """Linearly anisotropic emission on psi_n = mu_n (uniform in space): Phi_0 = Phi_2 = 0 and
+    Phi_1 = sum p mu^2, so q_n = 3 sigma_s1 mu_n sum p mu^2 / (4 pi) and q_n / (sigma_s1 mu_n) =
+    sum p mu^2 / (4 pi / 3).  For the octahedral patch sets that ratio is 0.978, 0.994 and 0.9986 at
+    na = 4, 8, 16 (3 s.f.) and tends to the continuum value 1 (the integral of mu^2 over the sphere
+    is 4 pi / 3); without the factor 3 it would be near 1/3."""
+    quad = qd.quadrature(na)
+    N, s1 = 3, 0.7
+    nd = 8 * na * na
+    psi = np.broadcast_to(quad["mu"][None, :, None, None], (1, nd, N, N)).copy()
+    sigma_s = np.zeros((2, 1, 1, N, N))
+    sigma_s[1] = s1
+    q = emission(psi, quad, sigma_s, np.zeros((1, N, N)))
+    sel = np.abs(quad["mu"]) > 0.05
+    ratio = q[0, sel, 1, 1] / (s1 * quad["mu"][sel])
+    assert np.allclose(ratio, ratio[0], rtol=1e-12)
+    assert abs(ratio[0] - ref) < 1.5e-3
+    assert 1.0 - 0.03 < ratio[0] < 1.0
