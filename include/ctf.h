@@ -277,6 +277,17 @@ size_t ctf_cnn_workspace_bytes(int batch, int h, int w);
  * the convolutions on bf16 MFMA with float32 accumulation; 0: float32 vector arithmetic. */
 int ctf_cnn_forward(const float* params, const float* in, float* out, int batch, int h, int w, int bf16,
                     void* workspace, size_t ws_bytes, void* stream);
+/* The same forward pass for callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): no workspace argument, and the call
+ * makes no allocation of any kind.  The three hidden activations live in a file-scope device array
+ * of 3 * 32 * 32768 float32 values (12 MiB) that each GPU the library runs on holds until the
+ * process ends, so batch * h * w must not exceed 32768 (else CTF_EINVAL, nothing launched).
+ * Every call on one GPU uses that GPU's one array: calls that overlap on one GPU (different
+ * streams, or host threads) race and must be ordered by the caller.  Nothing in the array needs
+ * clearing between calls; each layer writes all of its output.  Results equal ctf_cnn_forward's
+ * bit for bit (the same kernels). */
+int ctf_cnn_forward_noalloc(const float* params, const float* in, float* out, int batch, int h, int w,
+                            int bf16, void* stream);
 /* Mean-squared-error loss of net(in) against target[batch][1][h][w] (loss: device float64 scalar)
  * and its gradient grad (device float32, ctf_cnn_param_count() values). */
 int ctf_cnn_loss_grad(const float* params, const float* in, const float* target, int batch, int h,

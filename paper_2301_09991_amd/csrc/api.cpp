@@ -1481,6 +1481,16 @@ int ctf_cnn_forward(const float* params, const float* in, float* out, int batch,
   return CTF_OK;
 }
 
+int ctf_cnn_forward_noalloc(const float* params, const float* in, float* out, int batch, int h, int w, int bf16,
+                            void* stream) {
+  if (!params || !in || !out || batch < 1 || h < 1 || w < 1) return fail(CTF_EINVAL, "bad argument");
+  if (size_t(batch) * size_t(h) * size_t(w) > kCnnScratchPixels)
+    return fail(CTF_EINVAL, "batch * h * w exceeds the no-allocation limit of " +
+                                std::to_string(kCnnScratchPixels) + " pixels");
+  CTF_HIP(cnn_forward_noalloc(params, in, out, batch, h, w, bf16, static_cast<hipStream_t>(stream)));
+  return CTF_OK;
+}
+
 int ctf_cnn_loss_grad(const float* params, const float* in, const float* target, int batch, int h, int w,
                       int bf16, float* grad, double* loss, void* workspace, size_t ws_bytes, void* stream) {
   if (!params || !in || !target || !grad || !loss || !workspace || batch < 1 || h < 1 || w < 1)

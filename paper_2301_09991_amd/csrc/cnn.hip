@@ -8,6 +8,8 @@
 // activation is rounded to a bf16 value, so the MFMA operands are exact copies of it.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace ctf {
@@ -324,14 +326,55 @@ CnnWs carve(void* ws, int B, int H, int W) {
 }
 }  // namespace
 
+// Hidden activations of cnn_forward_noalloc: one array per GPU, held until the process ends.  In
+// host code its name is only a stand-in; the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) float scratch[3 * 32 * kCnnScratchPixels];
+
+namespace {
+// the four layers with the three hidden activations in h1, h2, h3 (32 channels each)
+hipError_t forward_layers(const float* theta, const float* in, float* h1, float* h2, float* h3, float* out,
+                          int B, int H, int W, int bf16, hipStream_t s) {
+  hipError_t e;
+  if ((e = fwd_layer<0>(in, theta, h1, B, H, W, bf16, s))) return e;
+  if ((e = fwd_layer<1>(h1, theta, h2, B, H, W, bf16, s))) return e;
+  if ((e = fwd_layer<2>(h2, theta, h3, B, H, W, bf16, s))) return e;
+  return fwd_layer<3>(h3, theta, out, B, H, W, bf16, s);
+}
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mutex;
+float* scratch_ptr[kMaxDevices] = {};
+
+// the device address of this GPU's scratch array, looked up once per device
+hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch))) != hipSuccess) return e;
+    scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = scratch_ptr[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 hipError_t cnn_forward(const float* theta, const float* in, float* out, int B, int H, int W, int bf16,
                        void* ws, hipStream_t s) {
   CnnWs c = carve(ws, B, H, W);
-  hipError_t e;
-  if ((e = fwd_layer<0>(in, theta, c.h1, B, H, W, bf16, s))) return e;
-  if ((e = fwd_layer<1>(c.h1, theta, c.h2, B, H, W, bf16, s))) return e;
-  if ((e = fwd_layer<2>(c.h2, theta, c.h3, B, H, W, bf16, s))) return e;
-  return fwd_layer<3>(c.h3, theta, out ? out : c.out, B, H, W, bf16, s);
+  return forward_layers(theta, in, c.h1, c.h2, c.h3, out ? out : c.out, B, H, W, bf16, s);
+}
+
+hipError_t cnn_forward_noalloc(const float* theta, const float* in, float* out, int B, int H, int W, int bf16,
+                               hipStream_t s) {
+  float* sc = nullptr;
+  hipError_t e = scratch_address(&sc);
+  if (e != hipSuccess) return e;
+  const size_t px = size_t(B) * H * W;
+  return forward_layers(theta, in, sc, sc + 32 * px, sc + 64 * px, out, B, H, W, bf16, s);
 }
 
 hipError_t cnn_loss_grad(const float* theta, const float* in, const float* target, int B, int H, int W,

@@ -206,6 +206,11 @@ int cnn_param_count();
 size_t cnn_workspace_bytes(int B, int H, int W);
 hipError_t cnn_forward(const float* theta, const float* in, float* out, int B, int H, int W, int bf16,
                        void* ws, hipStream_t s);
+// the same network with its hidden activations in a file-scope device array instead of a workspace
+// (batch * h * w <= kCnnScratchPixels; calls that overlap on one GPU share that array)
+constexpr size_t kCnnScratchPixels = 32768;
+hipError_t cnn_forward_noalloc(const float* theta, const float* in, float* out, int B, int H, int W, int bf16,
+                               hipStream_t s);
 hipError_t cnn_loss_grad(const float* theta, const float* in, const float* target, int B, int H, int W,
                          int bf16, float* grad, double* loss, void* ws, hipStream_t s);
 hipError_t cnn_adam(float* theta, float* m, float* v, const float* g, int n, int step, float lr, hipStream_t s);

@@ -28,6 +28,7 @@ EXPORTED = [
     "ctf_cnn_param_count", "ctf_cnn_workspace_bytes", "ctf_cnn_forward", "ctf_cnn_loss_grad",
     "ctf_cnn_adam", "ctf_cnn_attach", "ctf_cnn_enable", "ctf_cnn_sample",
     "ctf_solve_batch", "ctf_set_launch_shape", "ctf_get_launch_shape", "ctf_autotune",
+    "ctf_cnn_forward_noalloc",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
                  "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32", "corr_scatter",
@@ -93,6 +94,7 @@ def load():
         "ctf_cnn_workspace_bytes": (S, [I, I, I]),
         "ctf_cnn_forward": (I, [P, P, P, I, I, I, I, P, S, P]),
         "ctf_cnn_loss_grad": (I, [P, P, P, I, I, I, I, P, P, P, S, P]),
+        "ctf_cnn_forward_noalloc": (I, [P, P, P, I, I, I, I, P]),
         "ctf_cnn_adam": (I, [P, P, P, P, I, I, ctypes.c_float, P]),
         "ctf_cnn_attach": (I, [P, P]),
         "ctf_cnn_enable": (I, [P, I]),
@@ -182,6 +184,20 @@ def solve_batch(problems, psis, rtol, max_steps, steps_per_graph=1):
 
 def cnn_param_count():
     return load().ctf_cnn_param_count()
+
+
+# largest batch * h * w of cnn_forward_noalloc
+CNN_NOALLOC_MAX_PIXELS = 32768
+
+
+def cnn_forward_noalloc(params, x, out, bf16=True, stream=None):
+    """net(x) into out without any workspace or allocation (x: float32 [batch][3][h][w])."""
+    import torch
+    b, _, h, w = x.shape
+    s = stream if stream is not None else torch.cuda.current_stream(x.device)
+    _check(load().ctf_cnn_forward_noalloc(_ptr(params), _ptr(x), _ptr(out), b, h, w, int(bf16),
+                                          ctypes.c_void_p(s.cuda_stream)))
+    return out
 
 
 class Cnn:
