@@ -10,15 +10,29 @@ import bench
 
 
 def test_algorithmic_cost_model():
-    # p = 2: W = 5 taps; fused residual reads u, rhs and writes out (12 B) with 32W + 23 + 16W + 34 flops
-    b, f = bench.algorithmic_cost("pg32", 2, fused=True)
-    assert (b, f) == (12, 32 * 5 + 23 + 16 * 5 + 34) == (12, 297)
-    assert bench.algorithmic_cost("pg32", 2, fused=False) == (20, 32 * 5 + 23)
-    assert bench.algorithmic_cost("pg32_update", 2, fused=True)[0] == 12 + 16   # psi64 read and written
-    assert bench.algorithmic_cost("pg64", 2, fused=True)[0] == 8 + 4 + 4   # psi read; residual and fl32(psi) written
+    # the PG residual / sweep: 2b bytes (read psi, write the result) and the scope table's flop count
+    assert bench.algorithmic_cost("pg32", 2, fused=True) == (8, 220)
+    assert bench.algorithmic_cost("pg32", 1) == (8, 150)
+    assert bench.algorithmic_cost("pg64", 3, fused=True) == (16, 290)
+    assert bench.algorithmic_cost("pg32_update", 2) == (8, 220)
     assert bench.algorithmic_cost("moments", 2) == (4, 6)
     with pytest.raises(KeyError):
         bench.algorithmic_cost("no_such_class", 2)
+
+
+def test_implementation_cost_model():
+    # fused kernel stage by stage at p = 2 (W = 5 taps): A 2 x-sums + 2 y-passes, B 2 + 2, C 6 x-sums
+    # plus 2 products per tap, D 6 y-passes, each pass one multiply-add (2 flops) per tap: 42 W;
+    # k, emission and epilogue 57
+    W = 5
+    assert bench.implementation_flops("pg32", 2, fused=True) == 2 * W * (4 + 4 + 6 + 6) + 2 * W + 57 == 267
+    assert bench.implementation_flops("pg32", 2, fused=False) == 32 * W + 23
+    assert bench.implementation_flops("pgk32", 2) == 16 * W + 34
+    # full-approximation sweeps also read their right-hand side; the float64 residual also writes
+    # fl32(psi); the last float32 sweep reads and writes psi64
+    assert bench.implementation_bytes("pg32", 2) == 12
+    assert bench.implementation_bytes("pg64", 2) == 20
+    assert bench.implementation_bytes("pg32_update", 2) == 28
 
 
 def test_kernel_symbols_match_the_profiler_names():
@@ -36,26 +50,32 @@ def test_traffic_is_reported_only_for_the_measured_source(tmp_path, monkeypatch)
     kern = src / "kernels.hip"
     kern.write_text("// kernel source as measured\n")
     digest = hashlib.sha256(kern.read_bytes()).hexdigest()
-    (tmp_path / "profiles" / "traffic_k_x.txt").write_text(
+    (tmp_path / "profiles" / "traffic_k_x_wl.txt").write_text(
         "# comment: 1\nscaled bytes per launch: 123456\nkernels.hip sha256: %s\n" % digest)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
-    assert bench.read_traffic("k_x") == 123456.0
+    assert bench.read_traffic("k_x", "wl") == 123456.0
+    assert bench.read_traffic("k_x", "other") is None
     kern.write_text("// kernel source changed since\n")
-    assert bench.read_traffic("k_x") is None
-    assert bench.read_traffic("k_missing") is None
+    assert bench.read_traffic("k_x", "wl") is None
+    assert bench.read_traffic("k_missing", "wl") is None
 
 
-def test_committed_traffic_summary_is_well_formed():
-    path = os.path.join(os.path.dirname(bench.__file__), "profiles", "traffic_k_pg_fused_p2_f32.txt")
+@pytest.mark.parametrize("fname,dof", [("traffic_k_pg_fused_p2_f32_c1_mixed.txt", 256 * 256 * 512 * 2),
+                                       ("traffic_k_pg_fused_p2_f32_c4_learned.txt", 1024 * 1024 * 512)])
+def test_committed_traffic_summary_is_well_formed(fname, dof):
+    path = os.path.join(os.path.dirname(bench.__file__), "profiles", fname)
     vals = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     assert vals["kernel"] == "k_pg_fused<2, 0, float, false>"
-    scaled, alg = float(vals["scaled bytes per launch"]), float(vals["algorithmic bytes per launch"])
-    assert alg == 12 * 256 * 256 * 512 * 2
-    assert 1.0 <= scaled / alg < 1.5   # measured HBM bytes cannot undercut the arrays the kernel must move
+    fetch = float(vals["FETCH_SIZE KiB per dispatch"]) * 1024 * float(vals["FETCH scale"])
+    write = float(vals["WRITE_SIZE KiB per dispatch"]) * 1024 * float(vals["WRITE scale"])
+    assert abs(fetch + write - float(vals["scaled bytes per launch"])) < 1e-4 * (fetch + write)
+    scaled = float(vals["scaled bytes per launch"])
+    # the kernel reads x and its right-hand side and writes its output, 4 bytes each per DOF
+    assert 1.0 <= scaled / (12 * dof) < 3.0
 
 
 def test_more_than_one_gpu_is_refused_with_a_message():
