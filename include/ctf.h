@@ -59,8 +59,9 @@ enum { CTF_SMOOTH_UPWIND = 0, CTF_SMOOTH_FINEST = 1 };
 enum { CTF_R_MIXED_MASS = 0, CTF_R_LOW = 1, CTF_R_HIGH = 2 };
 
 typedef struct ctf_config {
-  int n;               /* nodes per side of the finest grid (N x N), 2 <= N <= 32768 (element
-                          offsets inside one ordinate plane are 32-bit) */
+  int n;               /* nodes per side of the finest grid (N x N), 2 <= N <= 8192 (byte
+                          offsets inside one ordinate plane, and inside the three emission
+                          moment planes of a group, are 32-bit) */
   double length;       /* side L of the square domain; h = L / N */
   int p;               /* ConvFEM degree 1..4 (ignored by CTF_UPWIND) */
   int na;              /* ordinates per face side, a power of two: n_dir = 8 na^2 */

@@ -39,37 +39,68 @@ __device__ __forceinline__ T& at(T* row, unsigned boff) {
   return *reinterpret_cast<T*>(reinterpret_cast<char*>(row) + boff);
 }
 
-// Anisotropic diffusivity of one direction component (eq. ano-k):
-//   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
-// The diffusivity helpers evaluate exactly as written: contraction is off inside them and the
-// fused multiply-adds are explicit (a contraction left to the compiler depends on the surrounding
-// code), so that every kernel forming k gives the same bits.
+// Raw buffer access to one plane of `bytes` bytes (< 2^31): a 32-bit vector byte offset (the
+// column) plus a 32-bit scalar byte offset (the row), so that a load costs no vector address
+// arithmetic at all; offsets past the plane read 0 (never reached: every offset is clamped).
+// Resource word 3 is the raw-buffer format of the gfx9 family.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const void* p, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, int(bytes), 0x00020000);
+}
 template <typename T>
-__device__ __forceinline__ T pg_k(T mu, T R, T Psi, T h, T akabs, T aksq, T eps) {
-#pragma clang fp contract(off)
-  return tmin(tmin(h * tabs(mu), qdiv(akabs * tabs(R) * h, eps + tabs(Psi))),
-              qdiv(aksq * R * R * h, tfma(tabs(mu) * Psi, Psi, eps)));
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff);
+template <>
+__device__ __forceinline__ float bload<float>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
 }
 
-// Isotropic diffusivity (the residual-based form with the mixed-mass residual R = R_x + R_y):
-//   k = min(sqrt((h mu)^2 + (h nu)^2), akabs |R| h / (eps + (|Psi_x| + |Psi_y|)/2),
-//           aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|)/2 (Psi_x^2 + Psi_y^2))),
-//   q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
+// Anisotropic diffusivity of one direction component (eq. ano-k):
+//   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
+// with the per-ordinate constants kmax = h |mu|, amu = |mu|, cabs = akabs h and csq = aksq h formed
+// once per block.  The diffusivity helpers evaluate exactly as written: contraction is off inside
+// them and the fused multiply-adds are explicit (a contraction left to the compiler depends on the
+// surrounding code), so that every kernel forming k gives the same bits.
+template <typename T>
+__device__ __forceinline__ T pg_k(T kmax, T amu, T R, T Psi, T cabs, T csq, T eps) {
+#pragma clang fp contract(off)
+  return tmin(tmin(kmax, qdiv(cabs * tabs(R), eps + tabs(Psi))), qdiv(csq * R * R, tfma(amu * Psi, Psi, eps)));
+}
+
 template <typename T>
 __device__ __forceinline__ T dot2(T a, T b, T c, T d) {
 #pragma clang fp contract(off)
   return tfma(a, b, c * d);
 }
 
+// Isotropic diffusivity (the residual-based form with the mixed-mass residual R = R_x + R_y):
+//   k = min(sqrt((h mu)^2 + (h nu)^2), akabs |R| h / (eps + (|Psi_x| + |Psi_y|)/2),
+//           aksq R^2 h / (eps + (|q Psi_x| + |q Psi_y|)/2 (Psi_x^2 + Psi_y^2))),
+//   q = (mu Psi_x + nu Psi_y) / (eps + Psi_x^2 + Psi_y^2)
+// with kmax = sqrt((h mu)^2 + (h nu)^2) (pg_kmax_iso), cabs = akabs h and csq = aksq h.
 template <typename T>
-__device__ __forceinline__ T pg_k_iso(T mu, T nu, T R, T px, T py, T h, T akabs, T aksq, T eps) {
+__device__ __forceinline__ T pg_kmax_iso(T mu, T nu, T h) {
+#pragma clang fp contract(off)
+  const T hm = h * mu, hn = h * nu;
+  return T(sqrt(dot2(hm, hm, hn, hn)));
+}
+template <typename T>
+__device__ __forceinline__ T pg_k_iso(T mu, T nu, T R, T px, T py, T kmax, T cabs, T csq, T eps) {
 #pragma clang fp contract(off)
   const T s2 = dot2(px, px, py, py);
   const T q = qdiv(dot2(mu, px, nu, py), eps + s2);
-  const T kabs = qdiv(akabs * tabs(R) * h, tfma(tabs(px) + tabs(py), T(0.5), eps));
-  const T ksq = qdiv(aksq * R * R * h, tfma((tabs(q * px) + tabs(q * py)) * T(0.5), s2, eps));
-  const T hm = h * mu, hn = h * nu;
-  return tmin(tmin(T(sqrt(dot2(hm, hm, hn, hn))), kabs), ksq);
+  const T kabs = qdiv(cabs * tabs(R), tfma(tabs(px) + tabs(py), T(0.5), eps));
+  const T ksq = qdiv(csq * R * R, tfma((tabs(q * px) + tabs(q * py)) * T(0.5), s2, eps));
+  return tmin(tmin(kmax, kabs), ksq);
 }
 
 // Emission of one ordinate from the flux moments: e0 + mu e1 + nu e2 (evaluated as written, so that
@@ -319,8 +350,6 @@ struct PGArgs {
   float* ky_out_f;
   float* psi_f;       // optional float copy of psi at the output cells
   double* acc64;      // mode 1, optional: acc64 += out - float(acc64) at the output cells
-  int iso;            // isotropic diffusivity
-  int r_estimate;     // its residual estimate (0 mixed mass, 1 degree p - 1, 2 degree p + 1)
 };
 
 // ---------------------------------------------------------------------------------------------
@@ -545,19 +574,21 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
 //   Psi_x = f(psi; m (x) d), Psi_y = f(psi; d (x) m) (psi with its halo rule),
 //   R = alpha_r mu (f(Psi; m (x) m) - Psi),  k = min(h|mu|, akabs |R| h/(eps+|Psi|), aksq R^2 h/(eps+|mu| Psi^2)).
 // The strip reads 64 + 4P columns, and writes k for its inner 64 - 2P columns.
-// RE selects the residual estimate of the isotropic form: 0 the mixed mass (above), 1 / 2 the
-// difference of the advection estimates mu Psi_x + nu Psi_y of degrees P and P - 1 / P + 1 (section
-// "Non-Linear Petrov-Galerkin Dissipation").  The other degree Q = P -+ 1 is x-passed on every
+// RE selects the diffusivity: 0 anisotropic (above); the isotropic form with R from the mixed mass
+// (3) or from the difference of the advection estimates mu Psi_x + nu Psi_y of degrees P and
+// P - 1 / P + 1 (1 / 2; section "Non-Linear Petrov-Galerkin Dissipation").  The other degree Q = P -+ 1 is x-passed on every
 // psi row into windows of 2P + Q + 1 rows, long enough to reach back to row o - Q when row o is
 // written.
 template <int P, int RE, typename T>
 __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
-  static_assert(RE == 0 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP), "residual estimate degree");
+  static_assert(RE == 0 || RE == 3 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP),
+                "residual estimate degree");
+  constexpr bool MIXED = RE == 0 || RE == 3;   // R from the mixed mass (anisotropic or isotropic k)
   constexpr int W = 2 * P + 1;
   constexpr int PQ = RE == 1 ? P - 1 : (RE == 2 ? P + 1 : 0);   // the other degree
   constexpr int WQ = 2 * PQ + 1;
-  constexpr int KQ = RE ? 2 * P + PQ + 1 : 1;
+  constexpr int KQ = MIXED ? 1 : 2 * P + PQ + 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
   constexpr int D = P + 2;              // LDS ring of Psi rows: the newest and the P rows above it
@@ -597,7 +628,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   const int gi = x0 + lane;
   const bool writer = lane >= P && lane < kStripW - P && gi < n && gi < xs + OW;
   const int yend = min(y0 + a.strip_h, n);
-  const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
+  const T eps = a.eps_k, ar = a.alpha_r;
+  const T cabs = a.akabs * h, csq = a.aksq * h, amu = tabs(mu), anu = tabs(nu);
+  const T kmx = h * amu, kmy = h * anu, kmi = pg_kmax_iso(mu, nu, h);
   // rows are loaded one ahead, unconditionally from clamped addresses (the halo rule is applied
   // when the row is written to LDS), so that no join waits for a load in flight
   T p0, p1;
@@ -630,7 +663,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       }
       wXd[t] = xd;
       wXm[t] = xm;
-      if constexpr (RE != 0) {
+      if constexpr (!MIXED) {
         // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row buffer; lq = lane for
         // every lane that writes
         const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
@@ -650,7 +683,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       gxr[lane] = yrot(wXd, cm, t);
       gyr[lane] = yrot(wXm, cd, t);
       __syncthreads();
-      if constexpr (RE == 0) {
+      if constexpr (MIXED) {
         T mx = 0, my = 0;
         if (lane >= P && lane < kStripW - P) {
 #pragma unroll
@@ -667,7 +700,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
         const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of Psi row o
         const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
         T kx, ky;
-        if constexpr (RE != 0) {
+        if constexpr (!MIXED) {
           // Psi of the other degree on row o: y-pass over the window rows o - Q .. o + Q
           T qx = 0, qy = 0;
 #pragma unroll
@@ -675,15 +708,15 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
             qx += cmq[v] * wQd[v];
             qy += cdq[v] * wQm[v];
           }
-          kx = ky = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, h, akabs, aksq, eps);
+          kx = ky = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
         } else {
           const T rx = ar * mu * (yrot(wMx, cm, t) - px);
           const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-          if (a.iso) {
-            kx = ky = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, h, akabs, aksq, eps);
+          if constexpr (RE == 3) {
+            kx = ky = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
           } else {
-            kx = pg_k(mu, rx, px, h, akabs, aksq, eps);
-            ky = pg_k(nu, ry, py, h, akabs, aksq, eps);
+            kx = pg_k(kmx, amu, rx, px, cabs, csq, eps);
+            ky = pg_k(kmy, anu, ry, py, cabs, csq, eps);
           }
         }
         const size_t ro = base + size_t(o) * n;
@@ -720,17 +753,20 @@ __device__ __forceinline__ int ring_back(int s, int off, int depth) { return s >
 __device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == depth ? 0 : s + 1; }
 
 // ACC: a.acc64 is given (mode 1), its values are prefetched with the other per-cell data.
-// RE: residual estimate of the isotropic form, as in k_pg_diffusivity (0 the mixed mass; 1 / 2 the
-// advection estimates of degrees P and P - 1 / P + 1, the other degree x-passed in stage A into
-// shifted windows that reach back to row r - 2P - Q when stage B forms k of row r - 2P).
+// RE: the diffusivity, as in k_pg_diffusivity (0 anisotropic; 3 isotropic with the mixed mass; 1 / 2
+// isotropic from the advection estimates of degrees P and P - 1 / P + 1, the other degree x-passed
+// in stage A into shifted windows that reach back to row r - 2P - Q when stage B forms k of row
+// r - 2P).
 template <int P, int RE, typename T, bool ACC>
 __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
-  static_assert(RE == 0 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP), "residual estimate degree");
+  static_assert(RE == 0 || RE == 3 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP),
+                "residual estimate degree");
+  constexpr bool MIXED = RE == 0 || RE == 3;   // R from the mixed mass (anisotropic or isotropic k)
   constexpr int W = 2 * P + 1;
   constexpr int PQ = RE == 1 ? P - 1 : (RE == 2 ? P + 1 : 0);   // the other degree
   constexpr int WQ = 2 * PQ + 1;
-  constexpr int KQ = RE ? 2 * P + PQ + 1 : 1;
+  constexpr int KQ = MIXED ? 1 : 2 * P + PQ + 1;
   constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
   constexpr int PR = 4 * P + 1;         // psi rows kept (r - 4P .. r)
   constexpr int GR = 3 * P + 1;         // Psi rows kept (r - 4P .. r - P)
@@ -760,16 +796,16 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     cm[t] = a.st.m[t];
     cd[t] = a.st.d[t];
     ck[t] = a.st.k[t];
-    if constexpr (sizeof(T) == 8 && P <= 2) {
-      // float64 up to p = 2: keep the taps in vector registers (occupancy is bound by LDS there, and
-      // in scalar registers they crowd out the loop's addresses, which then spill into vector lanes)
+    if constexpr (P <= 2) {
+      // up to p = 2: keep the taps in vector registers (in scalar registers they crowd out the
+      // loop's buffer resources and addresses, which then spill into vector lanes)
       asm volatile("" : "+v"(cm[t]));
       asm volatile("" : "+v"(cd[t]));
       asm volatile("" : "+v"(ck[t]));
     }
   }
   T cmq[WQ] = {}, cdq[WQ] = {};
-  if constexpr (RE != 0) {
+  if constexpr (!MIXED) {
 #pragma unroll
     for (int t = 0; t < WQ; ++t) {
       cmq[t] = a.st.mr[t];
@@ -792,7 +828,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const int kcl = clampi(col, 0, n - 1) - c0;   // lane of the nearest interior column (own lane inside)
   const int hidx = lane < 2 * P ? kStripW + lane : lane;   // halo lanes also write the P columns past 64
   const int yend = min(y0 + a.strip_h, n);
-  const T akabs = a.akabs, aksq = a.aksq, eps = a.eps_k, ar = a.alpha_r;
+  const T eps = a.eps_k, ar = a.alpha_r;
+  const T cabs = a.akabs * h, csq = a.aksq * h, amu = tabs(mu), anu = tabs(nu);
+  const T kmx = h * amu, kmy = h * anu, kmi = pg_kmax_iso(mu, nu, h);
   const T diag = a.beta * (tabs(mu) / h + tabs(nu) / h);
   double acc = 0.0;
   // loads are unconditional, from clamped addresses (halo rule and unused values applied at the
@@ -804,25 +842,38 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   const bool has_rhs = a.rhs != nullptr, p1mom = a.nmomE > 1;
   const T rsg = a.rhs_sign;
   const T* __restrict__ Eg = a.E + size_t(g) * a.nmomE * ncell;
-  const T* __restrict__ E1g = p1mom ? Eg + ncell : Eg;
-  const T* __restrict__ E2g = p1mom ? Eg + 2 * ncell : Eg;
   const T* __restrict__ sigg = a.L.sigma_t + size_t(g) * ncell;
   const T* __restrict__ rhsp = has_rhs ? a.rhs + base : Eg;
   const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
   const unsigned bc = unsigned(clampi(col, 0, n - 1)) * sizeof(T);
   const unsigned bo = unsigned(col) * sizeof(T), bof = unsigned(col) * sizeof(float);
-  // in-plane element offsets are 32-bit (n < 65536): row offsets cost one scalar multiply
+  // planes are below 2^29 bytes (n <= 8192): loads take the column as a vector byte offset and the
+  // row as a scalar one.  The per-cell planes E0, E1, E2 are consecutive, one resource covers them.
+  const unsigned pb = unsigned(ncell * sizeof(T));
+  const __amdgpu_buffer_rsrc_t r_psi = plane_rsrc(psi, pb), r_sig = plane_rsrc(sigg, pb),
+                               r_rh = plane_rsrc(rhsp, pb), r_e = plane_rsrc(Eg, p1mom ? 3 * pb : pb),
+                               r_y = plane_rsrc(yp, unsigned(ncell * 8));
+  const unsigned e1o = p1mom ? pb : 0u, e2o = p1mom ? 2 * pb : 0u;
+  // output planes (an absent one is never written), through buffer stores in the float32 residual
+  // and sweep; the float64 kernel and the sweep with the float64 update keep plain stores (their
+  // scalar registers are short)
+  constexpr bool BST = sizeof(T) == 4 && !ACC;
+  const __amdgpu_buffer_rsrc_t w_out = plane_rsrc(a.out ? a.out + base : nullptr, pb),
+                               w_outf = plane_rsrc(a.out_f ? a.out_f + base : nullptr, unsigned(ncell * 4)),
+                               w_psif = plane_rsrc(a.psi_f ? a.psi_f + base : nullptr, unsigned(ncell * 4)),
+                               w_acc = plane_rsrc(ACC ? a.acc64 + base : nullptr, unsigned(ncell * 8));
   auto load_row = [&](int r) {
-    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n);
-    p0 = at(psi + ro, b0);
-    p1 = at(psi + ro, b1);
-    const unsigned co = unsigned(clampi(r - 4 * P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
-    fe0 = at(Eg + co, bc);
-    fe1 = at(E1g + co, bc);
-    fe2 = at(E2g + co, bc);
-    frh = at(rhsp + co, bc);
-    fs = at(sigg + co, bc);
-    if (ACC) fy = at(yp + co, b64);
+    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n) * unsigned(sizeof(T));
+    p0 = bload<T>(r_psi, b0, ro);
+    p1 = bload<T>(r_psi, b1, ro);
+    const unsigned cr = unsigned(clampi(r - 4 * P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
+    const unsigned co = cr * unsigned(sizeof(T));
+    fe0 = bload<T>(r_e, bc, co);
+    fe1 = bload<T>(r_e, bc, co + e1o);
+    fe2 = bload<T>(r_e, bc, co + e2o);
+    frh = bload<T>(r_rh, bc, co);
+    fs = bload<T>(r_sig, bc, co);
+    if (ACC) fy = bload<double>(r_y, b64, cr * 8u);
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg);
@@ -859,7 +910,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         wXm[t] = xm;
         gxr[lane] = yrot(wXd, cm, t);
         gyr[lane] = yrot(wXm, cd, t);
-        if constexpr (RE != 0) {
+        if constexpr (!MIXED) {
           // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row; lq = lane on every lane
           // whose k is read (P .. 63 - P)
           const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
@@ -875,10 +926,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         }
       }
       // the other-degree estimates read Psi of their own lane only: no wait for its neighbours
-      if constexpr (RE == 0) __syncthreads();
+      if constexpr (MIXED) __syncthreads();
       // B: k of row r - 2P
       {
-        if constexpr (RE == 0) {
+        if constexpr (MIXED) {
           T mx = 0, my = 0;
 #pragma unroll
           for (int u = 0; u < W; ++u) {
@@ -894,7 +945,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
           const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
           T* const k0r = &s_k[t][0][P];
           T* const k1r = &s_k[t][1][P];
-          if constexpr (RE != 0) {
+          if constexpr (!MIXED) {
             // Psi of the other degree on row rk: y-pass over the window rows rk - Q .. rk + Q
             T qx = 0, qy = 0;
 #pragma unroll
@@ -902,20 +953,20 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
               qx += cmq[v] * wQd[v];
               qy += cdq[v] * wQm[v];
             }
-            const T kk = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, h, akabs, aksq, eps);
+            const T kk = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
             k0r[lane] = kk;
             k1r[lane] = kk;
-          } else if (a.iso) {
+          } else if constexpr (RE == 3) {
             const T rx = ar * mu * (yrot(wMx, cm, t) - px);
             const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-            const T kk = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, h, akabs, aksq, eps);
+            const T kk = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
             k0r[lane] = kk;
             k1r[lane] = kk;
           } else {
             const T rx = ar * mu * (yrot(wMx, cm, t) - px);
             const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-            k0r[lane] = pg_k(mu, rx, px, h, akabs, aksq, eps);
-            k1r[lane] = pg_k(nu, ry, py, h, akabs, aksq, eps);
+            k0r[lane] = pg_k(kmx, amu, rx, px, cabs, csq, eps);
+            k1r[lane] = pg_k(kmy, anu, ry, py, cabs, csq, eps);
           }
           if (edge_strip) {
             // columns outside the domain take k of the nearest interior column
@@ -965,21 +1016,36 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
         const T dx = kxc * yrot(wA1x, cm, t) + yrot(wA2x, cm, t) - psc * yrot(wA3x, cm, t);
         const T dy = kyc * yrot(wA1y, ck, t) + yrot(wA2y, ck, t) - psc * yrot(wA3y, ck, t);
-        const size_t ro = base + size_t(o) * n;
+        const unsigned orow = unsigned(o) * unsigned(n);
         T q = e0;
         if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
         if (has_rhs) q = tfma(rsg, rh, q);
         const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
-        if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
-        if (a.mode == 0) {
-          const T val = a.sign * rho;
-          if (a.out) at(a.out + ro, bo) = val;
-          if (a.out_f) at(a.out_f + ro, bof) = float(val);
-          acc += double(val) * double(val);
+        if constexpr (BST) {
+          if (a.psi_f) bstore(float(psc), w_psif, bof, orow * 4u);
+          if (a.mode == 0) {
+            const T val = a.sign * rho;
+            if (a.out) bstore(val, w_out, bo, orow * unsigned(sizeof(T)));
+            if (a.out_f) bstore(float(val), w_outf, bof, orow * 4u);
+            acc += double(val) * double(val);
+          } else {
+            const T un = psc + qdiv(rho, diag + a.beta * sig);
+            bstore(un, w_out, bo, orow * unsigned(sizeof(T)));
+            if (ACC) bstore(y64 + (double(un) - double(float(y64))), w_acc, unsigned(col) * 8u, orow * 8u);
+          }
         } else {
-          const T un = psc + qdiv(rho, diag + a.beta * sig);
-          at(a.out + ro, bo) = un;
-          if (ACC) at(a.acc64 + ro, unsigned(col) * 8u) = y64 + (double(un) - double(float(y64)));
+          const size_t ro = base + size_t(orow);
+          if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
+          if (a.mode == 0) {
+            const T val = a.sign * rho;
+            if (a.out) at(a.out + ro, bo) = val;
+            if (a.out_f) at(a.out_f + ro, bof) = float(val);
+            acc += double(val) * double(val);
+          } else {
+            const T un = psc + qdiv(rho, diag + a.beta * sig);
+            at(a.out + ro, bo) = un;
+            if (ACC) at(a.acc64 + ro, unsigned(col) * 8u) = y64 + (double(un) - double(float(y64)));
+          }
         }
       }
       __syncthreads();   // the next step overwrites ring slots read above
@@ -1521,6 +1587,11 @@ hipError_t launch_emission(const LevelDims& d, const T* phi, const T* ss, int nl
   return hipGetLastError();
 }
 
+// Kernel template code of the diffusivity: 0 anisotropic (eq. ano-k, mixed-mass R_x, R_y); the
+// isotropic form with R from the mixed mass (3), the degree P - 1 estimate (1) or the degree
+// P + 1 estimate (2).
+int pg_re(const PGParams& pp) { return pp.isotropic ? (pp.r_estimate ? pp.r_estimate : 3) : 0; }
+
 template <typename T>
 PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp, const PGLaunch<T>& o) {
   PGArgs<T> a{};
@@ -1532,8 +1603,6 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
   a.aksq = T(pp.alpha_ksq);
   a.beta = T(pp.beta);
   a.bc_vac = pp.bc_vac;
-  a.iso = pp.isotropic;
-  a.r_estimate = pp.r_estimate;
   a.psi = o.psi;
   a.E = o.E;
   a.nmomE = o.nmomE;
@@ -1561,11 +1630,15 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
   a.ntx = (n + ow - 1) / ow;
   const dim3 grid(a.ntx * ((n + a.strip_h - 1) / a.strip_h), L.dims.nd, L.dims.G);
   if (pp.r_estimate && !pp.isotropic) return hipErrorInvalidValue;
-  switch (p * 4 + pp.r_estimate) {
+  switch (p * 4 + pg_re(pp)) {
     case 4: hipLaunchKernelGGL((k_pg_diffusivity<1, 0, T>), grid, dim3(kStripW), 0, s, a); break;
     case 8: hipLaunchKernelGGL((k_pg_diffusivity<2, 0, T>), grid, dim3(kStripW), 0, s, a); break;
     case 12: hipLaunchKernelGGL((k_pg_diffusivity<3, 0, T>), grid, dim3(kStripW), 0, s, a); break;
     case 16: hipLaunchKernelGGL((k_pg_diffusivity<4, 0, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 7: hipLaunchKernelGGL((k_pg_diffusivity<1, 3, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 11: hipLaunchKernelGGL((k_pg_diffusivity<2, 3, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 15: hipLaunchKernelGGL((k_pg_diffusivity<3, 3, T>), grid, dim3(kStripW), 0, s, a); break;
+    case 19: hipLaunchKernelGGL((k_pg_diffusivity<4, 3, T>), grid, dim3(kStripW), 0, s, a); break;
     case 9: hipLaunchKernelGGL((k_pg_diffusivity<2, 1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 13: hipLaunchKernelGGL((k_pg_diffusivity<3, 1, T>), grid, dim3(kStripW), 0, s, a); break;
     case 17: hipLaunchKernelGGL((k_pg_diffusivity<4, 1, T>), grid, dim3(kStripW), 0, s, a); break;
@@ -1597,11 +1670,15 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   if (acc) hipLaunchKernelGGL((k_pg_fused<PP, RE, T, true>), grid, dim3(kStripW), 0, s, a); \
   else hipLaunchKernelGGL((k_pg_fused<PP, RE, T, false>), grid, dim3(kStripW), 0, s, a)
     const bool acc = a.acc64 != nullptr;
-    switch (p * 4 + pp.r_estimate) {
+    switch (p * 4 + pg_re(pp)) {
       case 4: CTF_FUSED(1, 0); break;
       case 8: CTF_FUSED(2, 0); break;
       case 12: CTF_FUSED(3, 0); break;
       case 16: CTF_FUSED(4, 0); break;
+      case 7: CTF_FUSED(1, 3); break;
+      case 11: CTF_FUSED(2, 3); break;
+      case 15: CTF_FUSED(3, 3); break;
+      case 19: CTF_FUSED(4, 3); break;
       case 9: CTF_FUSED(2, 1); break;
       case 13: CTF_FUSED(3, 1); break;
       case 17: CTF_FUSED(4, 1); break;
