@@ -46,6 +46,35 @@ def test_batch_equals_individual_solves(precision, steps_per_graph):
         assert np.array_equal(psi.cpu().numpy(), x.cpu().numpy())
 
 
+@pytest.mark.parametrize("precision,rtol,tol", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
+def test_batch_solutions_match_the_oracle(precision, rtol, tol):
+    """Uneven problems solved together by replays of one graph, in float64 and in float32 cycles
+    with float64 refinement, reach the oracle's own solution of each: the discrete equations solved
+    by restarted GMRES with the exact upwind transport sweep as preconditioner (no multigrid), to
+    1e-13.  The batch stops each problem at its own residual rtol; the error bound allows the
+    inverse operator's gain (at most ~1/sigma_a here) on that residual, with a factor 100 margin."""
+    import sys
+    from oracle import direct as odir
+    from oracle import multigrid as omg
+    from pairs import rel_w
+    ctf = _ctf()
+    sizes = [8, 12, 16, 10, 14]
+    ws = [Workload(f"bo{k}", N, 1.0, 2, 2, 1, 2, "iso", "box_quarter", seed=3100 + k) for k, N in enumerate(sizes)]
+    probs = [_problem(w, precision) for w in ws]
+    psis = [p.zeros() for p in probs]
+    print(f"[batch-oracle] precision={precision} sizes={sizes}", file=sys.stderr, flush=True)
+    ok, infos = ctf.solve_batch(probs, psis, rtol, 600, 2)
+    assert ok
+    for w, psi, info in zip(ws, psis, infos):
+        st, ss, src = make_inputs(w)
+        op = omg.Problem(w.N, w.L, w.p, w.na, st, ss, src, disc=omg.UPWIND)
+        ref, res = odir.gmres_solve(op, tol=1e-13)
+        assert res < 1e-12
+        assert info["rel_residual"] <= rtol
+        err = rel_w(psi.cpu().numpy(), ref, op.quad, op.h)
+        assert err < tol, (w.N, err)
+
+
 def test_batch_workload_sizes():
     ws = batch_workloads()
     assert len(ws) == 64

@@ -1,8 +1,14 @@
 """The learned coarse-grid correction on the GPU: network kernels against the float64 oracle, the
 training driver, the solver's fallback, and what the trained network gains over plain multigrid.
 
-Tolerances: float32-activation mode 1e-4 relative (float32 sums of <= 288 products per layer);
-bf16 mode 5e-2 relative (every activation and weight rounded to 8 significant bits, four layers).
+Tolerances, element by element against the largest reference value (max |x - x_ref| / max |x_ref|):
+* float32 activations: 1e-5 (float32 sums of <= 288 products per layer, four layers; measured
+  1e-7 to 5e-7);
+* bf16 activations: forward 2e-2, gradients 3e-2.  The input and the three stored hidden
+  activations are rounded to bf16 (relative 2^-9 each); a weight gradient sums products of a
+  back-propagated error, shaped by up to four rounded layers, and a rounded activation, so its
+  error is at most about 2 x 4 x 2^-9 = 1.6e-2 of the largest gradient, doubled for margin
+  (measured 9e-3 and 1.7e-2).  The loss: 2e-3 (measured 4.5e-4).
 """
 import numpy as np
 import pytest
@@ -27,7 +33,7 @@ def _data(B=2, H=12, W=20, seed=5):
     return theta, x, t
 
 
-@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
+@pytest.mark.parametrize("bf16,tol", [(False, 1e-5), (True, 2e-2)])
 def test_forward_matches_oracle(bf16, tol):
     import torch
     ctf, _ = _lib()
@@ -40,19 +46,21 @@ def test_forward_matches_oracle(bf16, tol):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("bf16,tol", [(False, 1e-4), (True, 5e-2)])
-def test_loss_and_gradient_match_oracle(bf16, tol):
+@pytest.mark.parametrize("shape", [(2, 12, 20, 5), (3, 16, 16, 7)])
+@pytest.mark.parametrize("bf16,tol_loss,tol_grad", [(False, 1e-5, 1e-5), (True, 2e-3, 3e-2)])
+def test_loss_and_gradient_match_oracle(bf16, tol_loss, tol_grad, shape):
     import torch
     ctf, _ = _lib()
-    theta, x, t = _data()
-    net = ctf.Cnn(2, 12, 20)
+    B, H, W, seed = shape
+    theta, x, t = _data(B, H, W, seed)
+    net = ctf.Cnn(B, H, W)
     grad = torch.zeros(theta.size, dtype=torch.float32, device="cuda")
     loss = net.loss_grad(torch.as_tensor(theta, device="cuda"), torch.as_tensor(x, device="cuda"),
                          torch.as_tensor(t, device="cuda"), grad, bf16=bf16).item()
     ref_loss, ref_g = ocnn.loss_and_grad(theta.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
     g = grad.cpu().numpy().astype(np.float64)
-    assert abs(loss - ref_loss) <= tol * ref_loss
-    assert np.linalg.norm(g - ref_g) <= tol * np.linalg.norm(ref_g)
+    assert abs(loss - ref_loss) <= tol_loss * ref_loss
+    assert np.abs(g - ref_g).max() <= tol_grad * np.abs(ref_g).max()
 
 
 def test_adam_matches_oracle():

@@ -71,18 +71,21 @@ def test_bf16_moments_refinement_reaches_fp64_solution():
 
 def test_pg_mixed_refinement_on_thick_cells():
     """Non-linear PG with float32 cycles in full-approximation form (optically thick cells, where
-    the cycle converges): the float64 residual falls below 1e-6, and the solution agrees with the
-    float64 oracle's to the accuracy that residual allows.  (The full-approximation form evaluates
-    the whole operator in float32, so its float64 residual levels off near 1e-7 relative.)"""
+    the cycle converges), run into its floor: the full-approximation form evaluates the whole
+    operator in float32, so the float64 residual levels off where it is one float32 rounding of the
+    operator's largest terms (measured 4.7e-7 relative here, after ~70 cycles).  At that floor the
+    solution is within 1e-6 relative L2 of the float64 oracle's converged solution (measured 8e-8)."""
     ctf = _ctf()
     w = workload(N=32, na=2, p=2, L=32.0, patch=4, source="box_center8", seed=0)
     op, gp = make_pair(w, "pg", "vac", precision=ctf.FP32_IR, n_inner=2)
-    psi_o, hist, ok = omg.solve(op, rtol=1e-10, max_cycles=150)
+    psi_o, hist, ok = omg.solve(op, rtol=1e-12, max_cycles=250)
     assert ok
     pd = gp.zeros()
     info = gp.solve(pd, 1e-6, 300)
     assert info["converged"], info
-    assert rel_w(to_host(pd), psi_o, op.quad, op.h) < 1e-5
+    info = gp.solve(pd, 1e-9, 60)           # on to the float32 floor
+    assert info["rel_residual"] < 1e-6
+    assert rel_w(to_host(pd), psi_o, op.quad, op.h) < 1e-6
 
 
 def test_mixed_precision_downscaled_mixed_workload():

@@ -74,14 +74,17 @@ def test_estimate_cycle_iterates(p, est):
 def test_low_estimate_mixed_refinement_on_thick_cells():
     """p = 2 with the low-degree estimate, float32 cycles in full-approximation form (the
     diffusivities formed by the float32 kernel) with float64 refinement, on optically thick cells:
-    the float64 residual falls below 1e-6 and the solution agrees with the float64 oracle's."""
+    the float64 residual falls below 1e-6 and, at the float32 floor, the solution is within 1e-6 of
+    the float64 oracle's."""
     from paper_2301_09991_amd import ctf
     print("mixed refinement p=2 low", file=sys.stderr, flush=True)
     w = workload(N=32, na=2, p=2, L=32.0, patch=4, source="box_center8", seed=0)
     op, gp = make_pair(w, "pg", "vac", precision=ctf.FP32_IR, n_inner=2, isotropic=True, r_estimate="low")
-    psi_o, hist, ok = omg.solve(op, rtol=1e-10, max_cycles=150)
+    psi_o, hist, ok = omg.solve(op, rtol=1e-12, max_cycles=250)
     assert ok
     pd = gp.zeros()
     info = gp.solve(pd, 1e-6, 300)
     assert info["converged"], info
-    assert rel_w(to_host(pd), psi_o, op.quad, op.h) < 1e-5
+    info = gp.solve(pd, 1e-9, 60)           # on to the float32 floor of the full-approximation form
+    assert info["rel_residual"] < 1e-6
+    assert rel_w(to_host(pd), psi_o, op.quad, op.h) < 1e-6
