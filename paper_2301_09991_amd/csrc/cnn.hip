@@ -19,8 +19,10 @@ namespace {
 constexpr int kB = 256;
 constexpr int kC[5] = {3, 32, 32, 32, 1};
 
-typedef short v4s_t __attribute__((ext_vector_type(4)));
+typedef short v8s_t __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v8bf_t as_bf16x8(v8s_t v) { return __builtin_bit_cast(v8bf_t, v); }
 
 __device__ __forceinline__ unsigned short to_bf16(float x) {
   unsigned int u = __float_as_uint(x);
@@ -71,7 +73,8 @@ __global__ __launch_bounds__(kB) void k_conv_fwd_f32(const float* __restrict__ i
 
 // ---- forward on MFMA: implicit GEMM D[pixel][c_out] = sum_k A[pixel][k] Bw[k][c_out], with
 // k = c_in * 9 + tap; one wave computes 16 consecutive pixels of a row for all output channels
-// (NT tiles of 16 channels) with v_mfma_f32_16x16x16_bf16.
+// (NT tiles of 16 channels) with gfx950's v_mfma_f32_16x16x32_bf16 (K = 32 per instruction:
+// 288 = 9 x 32 for the 32-channel layers, one zero-padded instruction for the 3-channel input).
 template <int CI, int CO>
 __global__ __launch_bounds__(64) void k_conv_fwd_mfma(const float* __restrict__ in, const float* __restrict__ W,
                                                       const float* __restrict__ bias, float* __restrict__ out,
@@ -88,12 +91,12 @@ __global__ __launch_bounds__(64) void k_conv_fwd_mfma(const float* __restrict__ 
 #pragma unroll
   for (int t = 0; t < NT; ++t) acc[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
   const float* src = in + size_t(b) * CI * hw;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    v4s_t a;
-    v4s_t bw[NT];
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    v8s_t a;
+    v8s_t bw[NT];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = k0 + 4 * kq + j;
+    for (int j = 0; j < 8; ++j) {
+      const int k = k0 + 8 * kq + j;
       float av = 0.f;
       int ci = 0, tap = 0;
       if (k < K) {
@@ -111,7 +114,8 @@ __global__ __launch_bounds__(64) void k_conv_fwd_mfma(const float* __restrict__ 
       }
     }
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, bw[t], acc[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(a), as_bf16x8(bw[t]), acc[t], 0, 0, 0);
   }
   // lane holds pixels 4*kq .. 4*kq+3 of output channel 16 t + i
 #pragma unroll

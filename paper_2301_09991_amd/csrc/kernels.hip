@@ -209,13 +209,15 @@ __global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __r
 
 // BF16 MFMA form of the moment contraction (float32 psi in memory):
 //   Phi[m][cell] = sum_n W[m][n] psi[n][cell],  W = (w, w mu, w nu),
-// as a [16 x n_dir] x [n_dir x cells] product on v_mfma_f32_16x16x16_bf16 with float32
-// accumulation (rows 3..15 of W are zero).  psi is rounded to bf16 once; the weights are
-// carried as a bf16 pair (hi + lo, two MFMAs per K-chunk) so that they keep ~16 bits.
-// A block owns 64 cells (four 16-cell MFMA tiles); its four waves each take a quarter of the
-// ordinates, and the quarters are summed in a fixed order through LDS.
-typedef short v4s_t __attribute__((ext_vector_type(4)));
+// as a [16 x n_dir] x [n_dir x cells] product on gfx950's v_mfma_f32_16x16x32_bf16 (K = 32
+// ordinates per instruction) with float32 accumulation (rows 3..15 of W are zero).  psi is
+// rounded to bf16 once; the weights are carried as a bf16 pair (hi + lo, two MFMAs per K-chunk)
+// so that they keep ~16 bits.  A block owns 64 cells (four 16-cell MFMA tiles); its four waves
+// each take a quarter of the ordinates, and the quarters are summed in a fixed order through LDS.
+typedef short v8s_t __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ v8bf_t as_bf16x8(v8s_t v) { return __builtin_bit_cast(v8bf_t, v); }
 
 __device__ __forceinline__ unsigned short bf16_rne(float x) {
   unsigned int u = __float_as_uint(x);
@@ -235,17 +237,18 @@ __global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, con
   const int g = blockIdx.y;
   const int nd = L.dims.nd;
   const int per = nd / 4;                     // ordinates of this wave (a multiple of 2 at least)
-  const int i = lane % 16, kq = lane / 16;    // A row / B column, and the K quarter of the lane
+  const int i = lane % 16, kq = lane / 16;    // A row / B column, and the K eighth-block of the lane
   v4f_t acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = v4f_t{0.f, 0.f, 0.f, 0.f};
   const float* base = psi + size_t(g) * nd * ncell;
-  for (int n0 = wave * per; n0 < (wave + 1) * per; n0 += 16) {
-    v4s_t ahi, alo;
-    v4s_t b[4];
+  // K = 32 ordinates per MFMA: lane (i, kq) holds ordinates n0 + 8 kq .. n0 + 8 kq + 7
+  for (int n0 = wave * per; n0 < (wave + 1) * per; n0 += 32) {
+    v8s_t ahi, alo;
+    v8s_t b[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + 4 * kq + j;
+    for (int j = 0; j < 8; ++j) {
+      const int n = n0 + 8 * kq + j;
       const bool inK = n < (wave + 1) * per;
       float wv = 0.f;
       if (inK && i < 3) wv = L.w[n] * (i == 0 ? 1.f : (i == 1 ? L.mu[n] : L.nu[n]));
@@ -261,8 +264,8 @@ __global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, con
     }
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ahi, b[t], acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(alo, b[t], acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ahi), as_bf16x8(b[t]), acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(alo), as_bf16x8(b[t]), acc[t], 0, 0, 0);
     }
   }
   // D layout: lane holds rows 4*(lane/16) .. +3 of column lane % 16; rows 0..2 are the moments
