@@ -129,7 +129,8 @@ typedef struct ctf_solve_info {
 } ctf_solve_info;
 
 /* Fill cfg with the paper's defaults: p = 1, na = 4, vacuum boundaries, upwind sweeps n_j = 2,
- * n_pg = 2, beta_pg = 3, alpha_r = 3, eps_k = 1e-3, FP64, n_inner = 2, no learned correction. */
+ * n_pg = 2, beta_pg = 3, alpha_r = 3, eps_k = 1e-3, FP64, no learned correction; and this library's
+ * n_inner = 4 float32 cycles per refinement step (the paper has no mixed precision). */
 void ctf_default_config(ctf_config* cfg);
 
 /* Bytes of device workspace a problem with this configuration needs (0 on invalid cfg; the

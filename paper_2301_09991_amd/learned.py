@@ -29,7 +29,7 @@ def init_params(seed, device="cuda"):
     return torch.as_tensor(theta, device=device)
 
 
-def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=2, max_growth=1.0,
+def make_problem(w, inputs, cnn_level, precision=ctf.FP64, disc=ctf.UPWIND, n_inner=4, max_growth=1.0,
                  max_uses=2, hemisphere=False, coupled=False):
     st, ss, src = inputs
     cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
