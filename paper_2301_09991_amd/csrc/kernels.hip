@@ -27,6 +27,12 @@ __device__ __forceinline__ double tfma(double a, double b, double c) { return __
 // serve the refinement's inner cycles), float64 exactly rounded.
 __device__ __forceinline__ float qdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+// a / b with the reciprocal rb of b formed once for several quotients by the same b: float32 as
+// a * rb (rb = qrcp(b), within 2 ulp), float64 exactly rounded (rb unused)
+__device__ __forceinline__ float qrcp(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double qrcp(double) { return 0.0; }
+__device__ __forceinline__ float qdivr(float a, float, float rb) { return a * rb; }
+__device__ __forceinline__ double qdivr(double a, double b, double) { return a / b; }
 
 // Element at a 32-bit byte offset from a wave-uniform row pointer, so that the access is a scalar
 // base plus a 32-bit vector offset (no 64-bit vector address arithmetic per access).
@@ -1170,7 +1176,8 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
           if (out_f) out_f[plane + cell] = float(val);
           acck += double(val) * double(val);
         } else {
-          out[plane + cell] = pc + rho / (amu + anu + sig);
+          const T dd = amu + anu + sig;
+          out[plane + cell] = pc + qdivr(rho, dd, qrcp(dd));
         }
         prev = pc;
       }
@@ -1270,7 +1277,8 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
     const T y = (t > 0 || prev_in) ? eprev : (yvac ? T(0) : c);
     const T sig = sg[t];
     const T r = (SCAT ? rh[t] + q[t] : rh[t]) - amu * (c - x) - anu * (c - y) - sig * c;
-    const T enew = c + r / (amu + anu + sig);
+    const T dd = amu + anu + sig;
+    const T enew = c + qdivr(r, dd, qrcp(dd));
     if (acc) acc[plane + cell] = av[t] + enew;
     else xout[plane + cell] = enew;
     eprev = c;
@@ -1341,9 +1349,9 @@ __global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<
       if (XMODE == 1) return src[size_t(jj >> 1) * nc + (ii >> 1)];
       return T(0);
     };
-    auto sweep = [&](T c, T x, T y, T r, T sig) -> T {
+    auto sweep = [&](T c, T x, T y, T r, T sig, T d, T rd) -> T {
       const T rr = r - amu * (c - x) - anu * (c - y) - sig * c;
-      return c + rr / (amu + anu + sig);
+      return c + qdivr(rr, d, rd);
     };
     T ec[R], ex[R], exx[R], rc[R], rx[R], av[R];
 #pragma unroll
@@ -1360,7 +1368,8 @@ __global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<
     // the upwind row (its values are used only when it lies inside the domain)
     const T hc = value(juc, i), hx = value(juc, iuc), hh = value(juuc, i);
     const T hr = rp[unsigned(juc) * unsigned(n) + i];
-    T e1prev = sweep(hc, x1 ? hx : (xvac ? T(0) : hc), y2 ? hh : (yvac ? T(0) : hc), hr, hs);
+    const T dh = amu + anu + hs;
+    T e1prev = sweep(hc, x1 ? hx : (xvac ? T(0) : hc), y2 ? hh : (yvac ? T(0) : hc), hr, hs, dh, qrcp(dh));
     T e0c_prev = hc, e0x_prev = hx;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
@@ -1368,9 +1377,14 @@ __global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<
       const int j = down ? j0 + t : j0 - t;
       const bool yin = t > 0 || y1;
       const T c = ec[t], cx = ex[t];
-      const T e1c = sweep(c, x1 ? cx : (xvac ? T(0) : c), yin ? e0c_prev : (yvac ? T(0) : c), rc[t], sc[t]);
-      const T e1x = sweep(cx, x2 ? exx[t] : (xvac ? T(0) : cx), yin ? e0x_prev : (yvac ? T(0) : cx), rx[t], sxv[t]);
-      const T e2 = sweep(e1c, x1 ? e1x : (xvac ? T(0) : e1c), yin ? e1prev : (yvac ? T(0) : e1c), rc[t], sc[t]);
+      // one reciprocal per cell: the two sweeps at (i, j) share it
+      const T dc = amu + anu + sc[t], dx = amu + anu + sxv[t];
+      const T rdc = qrcp(dc), rdx = qrcp(dx);
+      const T e1c = sweep(c, x1 ? cx : (xvac ? T(0) : c), yin ? e0c_prev : (yvac ? T(0) : c), rc[t], sc[t], dc, rdc);
+      const T e1x = sweep(cx, x2 ? exx[t] : (xvac ? T(0) : cx), yin ? e0x_prev : (yvac ? T(0) : cx), rx[t], sxv[t],
+                          dx, rdx);
+      const T e2 = sweep(e1c, x1 ? e1x : (xvac ? T(0) : e1c), yin ? e1prev : (yvac ? T(0) : e1c), rc[t], sc[t], dc,
+                         rdc);
       const unsigned cell = unsigned(j) * unsigned(n) + i;
       op[cell] = acc ? av[t] + e2 : e2;
       e0c_prev = c;
