@@ -411,6 +411,42 @@ __device__ __forceinline__ T yrot(const T (&w)[W], const T* c, int t) {
   return s;
 }
 
+// x-pass of an antisymmetric stencil (c[P] = 0, c[P + u] = -c[P - u] in exact arithmetic: the
+// first-derivative stencils) at the centre v[P] of the row values v[0 .. 2P]:
+// sum_u c[P + u] (v[P + u] - v[P - u]), one instruction less than the full W-tap sum
+template <int P, typename T>
+__device__ __forceinline__ T xanti(const T* v, const T* c) {
+  T s = c[P + 1] * (v[P + 1] - v[P - 1]);
+#pragma unroll
+  for (int u = 2; u <= P; ++u) s = tfma(c[P + u], v[P + u] - v[P - u], s);
+  return s;
+}
+
+// the same as a y-pass over a rotating window (the slot order of yrot)
+template <typename T, int W>
+__device__ __forceinline__ T yanti(const T (&w)[W], const T* c, int t) {
+  constexpr int P = (W - 1) / 2;
+  T s = c[P + 1] * (w[(t + 2 + P) % W] - w[(t + P) % W]);
+#pragma unroll
+  for (int u = 2; u <= P; ++u) s = tfma(c[P + u], w[(t + 1 + P + u) % W] - w[(t + 1 + P - u) % W], s);
+  return s;
+}
+
+// The k-Diff term of eqs. kxx / kyy, k_c f(psi; w) + f(k psi; w) - psi_c f(k; w) with w = x-pass (x)
+// y-pass, from the windows of the three x-passes (a1 = psi, a2 = k psi, a3 = k): one y-pass over
+// the rows a2 + k_c a1 - psi_c a3 (k_c, psi_c are the output node's values)
+template <typename T, int W>
+__device__ __forceinline__ T ykdiff(const T (&a1)[W], const T (&a2)[W], const T (&a3)[W], const T* c, int t, T kc,
+                                    T pc) {
+  T s = 0;
+#pragma unroll
+  for (int u = 0; u < W; ++u) {
+    const int j = (t + 1 + u) % W;
+    s += c[u] * tfma(-pc, a3[j], tfma(kc, a1[j], a2[j]));
+  }
+  return s;
+}
+
 // Residual with given diffusivities (k_x, k_y read with a copied halo):
 //   rho = rhs_sign rhs + q - mu Psi_x - nu Psi_y - D_x - D_y - sigma_t psi,
 //   D = k_c f(psi; w) + f(k psi; w) - psi_c f(k; w)   (eqs. kxx, kyy as written).
@@ -517,11 +553,11 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
       const double y64 = fy;
       load_row(r + 1);   // past the last row this reloads a clamped row, unused
       __syncthreads();
-      T xd = 0, xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
+      const T xd = xanti<P>(rp + lane, cd);
+      T xm = 0, xk = 0, a2x = 0, a3x = 0, a2y = 0, a3y = 0;
 #pragma unroll
       for (int u = 0; u < W; ++u) {
         const T v = rp[lane + u], kv = rk[lane + u], qv = rq[lane + u];
-        xd += cd[u] * v;
         xm += cm[u] * v;
         xk += ck[u] * v;
         a2x += ck[u] * (kv * v);
@@ -540,9 +576,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
       if (o >= y0 && gi < n) {
         const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of row o
         const T pc = s_row[cs][0][lane + P], kxc = s_row[cs][1][lane + P], kyc = s_row[cs][2][lane + P];
-        const T px = yrot(wXd, cm, t), py = yrot(wXm, cd, t);
-        const T dx = kxc * yrot(wXk, cm, t) + yrot(wA2x, cm, t) - pc * yrot(wA3x, cm, t);
-        const T dy = kyc * yrot(wXm, ck, t) + yrot(wA2y, ck, t) - pc * yrot(wA3y, ck, t);
+        const T px = yrot(wXd, cm, t), py = yanti(wXm, cd, t);
+        const T dx = ykdiff(wXk, wA2x, wA3x, cm, t, kxc, pc);
+        const T dy = ykdiff(wXm, wA2y, wA3y, ck, t, kyc, pc);
         const size_t ro = base + size_t(o) * n;
         T q = e0;
         if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
@@ -553,7 +589,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
           const T val = a.sign * rho;
           if (a.out) at(a.out + ro, bo) = val;
           if (a.out_f) at(a.out_f + ro, bof) = float(val);
-          acc += double(val) * double(val);
+          if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
         } else {
           const T un = pc + qdiv(rho, diag + a.beta * sig);
           at(a.out + ro, bo) = un;
@@ -563,7 +599,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
       ring = ring + 1 == D ? 0 : ring + 1;
     }
   }
-  if (a.partial) {
+  // norms are float64 only (a float32 launch with partial sums is refused by launch_pg)
+  if (sizeof(T) == 8 && a.partial) {
     // wave-level reduction in a fixed order (deterministic)
     __shared__ double red[kStripW];
     red[lane] = acc;
@@ -663,13 +700,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : p1;
       load_row(r + 1);   // past the last row this reloads a clamped row, unused
       __syncthreads();
-      T xd = 0, xm = 0;
+      const T xd = xanti<P>(s_psi + lane, cd);
+      T xm = 0;
 #pragma unroll
-      for (int u = 0; u < W; ++u) {
-        const T v = s_psi[lane + u];
-        xd += cd[u] * v;
-        xm += cm[u] * v;
-      }
+      for (int u = 0; u < W; ++u) xm += cm[u] * s_psi[lane + u];
       wXd[t] = xd;
       wXm[t] = xm;
       if constexpr (!MIXED) {
@@ -690,7 +724,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
       T* const gxr = s_g[ring][0];
       T* const gyr = s_g[ring][1];
       gxr[lane] = yrot(wXd, cm, t);
-      gyr[lane] = yrot(wXm, cd, t);
+      gyr[lane] = yanti(wXm, cd, t);
       __syncthreads();
       if constexpr (MIXED) {
         T mx = 0, my = 0;
@@ -908,17 +942,14 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       T* const gxr = &s_g[sg][0][P];
       T* const gyr = &s_g[sg][1][P];
       {
-        T xd = 0, xm = 0;
+        const T xd = xanti<P>(prow + lane, cd);
+        T xm = 0;
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-          const T v = prow[lane + u];
-          xd += cd[u] * v;
-          xm += cm[u] * v;
-        }
+        for (int u = 0; u < W; ++u) xm += cm[u] * prow[lane + u];
         wXd[t] = xd;
         wXm[t] = xm;
         gxr[lane] = yrot(wXd, cm, t);
-        gyr[lane] = yrot(wXm, cd, t);
+        gyr[lane] = yanti(wXm, cd, t);
         if constexpr (!MIXED) {
           // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row; lq = lane on every lane
           // whose k is read (P .. 63 - P)
@@ -1023,8 +1054,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
         const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
         const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
         const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
-        const T dx = kxc * yrot(wA1x, cm, t) + yrot(wA2x, cm, t) - psc * yrot(wA3x, cm, t);
-        const T dy = kyc * yrot(wA1y, ck, t) + yrot(wA2y, ck, t) - psc * yrot(wA3y, ck, t);
+        const T dx = ykdiff(wA1x, wA2x, wA3x, cm, t, kxc, psc);
+        const T dy = ykdiff(wA1y, wA2y, wA3y, ck, t, kyc, psc);
         const unsigned orow = unsigned(o) * unsigned(n);
         T q = e0;
         if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
@@ -1036,7 +1067,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
             const T val = a.sign * rho;
             if (a.out) bstore(val, w_out, bo, orow * unsigned(sizeof(T)));
             if (a.out_f) bstore(float(val), w_outf, bof, orow * 4u);
-            acc += double(val) * double(val);
+            if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
           } else {
             const T un = psc + qdiv(rho, diag + a.beta * sig);
             bstore(un, w_out, bo, orow * unsigned(sizeof(T)));
@@ -1049,7 +1080,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
             const T val = a.sign * rho;
             if (a.out) at(a.out + ro, bo) = val;
             if (a.out_f) at(a.out_f + ro, bof) = float(val);
-            acc += double(val) * double(val);
+            if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
           } else {
             const T un = psc + qdiv(rho, diag + a.beta * sig);
             at(a.out + ro, bo) = un;
@@ -1062,7 +1093,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       sg = ring_next(sg, GR);
     }
   }
-  if (a.partial) {
+  // norms are float64 only (a float32 launch with partial sums is refused by launch_pg)
+  if (sizeof(T) == 8 && a.partial) {
     __shared__ double red[kStripW];
     red[lane] = acc;
     __syncthreads();
@@ -1670,6 +1702,7 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
                      const PGLaunch<T>& o, hipStream_t s) {
+  if (sizeof(T) == 4 && o.partial) return hipErrorInvalidValue;   // the float32 kernels form no norms
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
