@@ -137,7 +137,10 @@ void ctf_default_config(ctf_config* cfg);
  * reason is in ctf_last_error()). */
 size_t ctf_workspace_bytes(const ctf_config* cfg);
 
-/* Create a problem.
+/* Create a problem: the fixed-source multigroup discrete-ordinates equations of section
+ * "Boltzmann Transport Equation" (no fission term) on the grid of eq. discretised_hfm, with the
+ * ordinates of section "Discrete Ordinates" and the level hierarchy of section "Space-Angle
+ * Multigrid".
  *   sigma_t  device float64 [G][N][N]             total cross-section (> 0 or = 0 for void)
  *   sigma_s  device float64 [L_s+1][G][G][N][N]   scattering sigma_{s,l}(g_from -> g_to) stored
  *                                                 [l][g_to][g_from]; L_s = scatter_order
@@ -212,14 +215,20 @@ int ctf_restrict(ctf_problem* prob, int level, const double* fine, double* coars
 /* UpSamp from level+1 to level: every fine value copies its parent cell and ordinate. */
 int ctf_prolong(ctf_problem* prob, int level, const double* coarse, double* fine);
 
-/* One sawtooth cycle in place on psi (device float64 [G][n_dir][N][N]).  If rel_res is non-NULL
- * the call synchronises and stores ||rho(psi_in)||_W / ||b||_W of the input psi. */
+/* One sawtooth cycle (section "Space-Angle Multigrid" and its sawtooth-cycle figure): the finest
+ * residual restricted to every level, Jacobi sweeps from zero on the coarsest level, UpSamp and
+ * sweeps level by level up to the finest, psi += e, then n_pg finest sweeps (eq. matrix_full with
+ * beta_pg for ConvFEM).  In place on psi (device float64 [G][n_dir][N][N]); with precision !=
+ * CTF_FP64 one call is one refinement step (as in ctf_solve).  If rel_res is non-NULL the call
+ * synchronises and stores ||rho(psi_in)||_W / ||b||_W of the input psi. */
 int ctf_mg_cycle(ctf_problem* prob, double* psi, double* rel_res);
 
 /* Cycle until ||rho||_W / ||b||_W <= rtol (checked before every cycle) or max_cycles cycles;
  * in place from the given psi (warm start).  With precision != CTF_FP64 every outer step
- * evaluates rho in float64, runs n_inner float32 cycles on the correction equation (diffusivities
- * frozen at the outer psi) and adds the correction in float64.  Synchronous.
+ * evaluates rho in float64, runs n_inner float32 cycles and updates psi in float64: for the
+ * non-linear PG the cycles act on the full-approximation problem A32(u) = A32(fl32(psi)) + rho
+ * (diffusivities re-formed from u in every float32 evaluation), for the linear discretisations on
+ * the correction equation A e = rho.  Synchronous.
  * Returns CTF_OK, CTF_NOT_CONVERGED, or an error (CTF_ENONFINITE on a NaN/Inf residual). */
 int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_solve_info* info);
 
