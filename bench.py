@@ -484,6 +484,10 @@ def step_throughput(wname, steps, warmup, launch_shape=None, log=None):
                  "implementation_flops_per_dof": impl_f,
                  "implementation_tflops": w.dof * impl_f / avg_s / 1e12,
                  "implementation_bytes_per_dof": impl_b})
+    if roof["bound"] == "alu":
+        # packed FP32 instructions are not used (build flags), so the vector rate this code can reach
+        # is half the published FP32 figure; FP64 vector math has no packed form
+        roof["frac_of_unpacked_vector_peak"] = tflops / (valu_peak / 2 if dom.endswith("32") else valu_peak)
     if log:
         log(f"{w.name}: {steps} steps in {dt:.3f} s ({1e3 * dt / steps:.3f} ms/step), dominant {sym} "
             f"{avg_s * 1e3:.3f} ms")
