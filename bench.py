@@ -375,7 +375,8 @@ def duct_study(log):
 def batched(log):
     """The batched workload: 64 problems with sizes drawn from {64, ..., 384}^2, p = 2, 512
     ordinates, one group, upwind discretisation, float32 cycles + float64 refinement to 1e-6, all
-    solved by replays of one captured HIP graph; launch shapes autotuned per size."""
+    solved by replays of one captured HIP graph (launch shapes autotuned per size), then again from
+    zero in one launch of the persistent work-queue kernel."""
     import tempfile
     import torch
     from paper_2301_09991_amd import ctf
@@ -399,7 +400,20 @@ def batched(log):
     dt = time.perf_counter() - t0
     cyc = [i["cycles"] for i in infos]
     log(f"batched: {len(ws)} problems, {dof} DOF, converged={ok}, {dt:.3f} s")
-    return {"problems": len(ws), "dof": dof, "converged": ok, "seconds": dt,
+    # the same solves again from zero in one launch of the persistent work-queue kernel
+    for x in psis:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ok_p, infos_p = ctf.solve_batch_persistent(probs, psis, 1e-6, 400)
+    dt_p = time.perf_counter() - t0
+    cyc_p = [i["cycles"] for i in infos_p]
+    log(f"batched, persistent launch: converged={ok_p}, {dt_p:.3f} s")
+    persistent = {"converged": ok_p, "seconds": dt_p, "cycles_equal_to_graph_form": cyc_p == cyc,
+                  "dof_updates_per_s": sum(w.dof * c for w, c in zip(ws, cyc_p)) / dt_p,
+                  "max_rel_residual": max(i["rel_residual"] for i in infos_p),
+                  "graph_over_persistent_time": dt / dt_p}
+    return {"problems": len(ws), "dof": dof, "converged": ok, "seconds": dt, "persistent_launch": persistent,
             "discretisation": "upwind",
             "substitute": "the batched workload is specified with biquadratic ConvFEM + PG; the non-linear "
                           "PG cycle does not contract on these optically thin media, so the solves to 1e-6 "

@@ -245,6 +245,29 @@ int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_s
 int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, double rtol,
                     int max_steps, int steps_per_graph, ctf_solve_info* infos);
 
+/* The same solve in ONE launch of a persistent kernel (upwind discretisation, any precision; no
+ * scattering-coupled sweeps, no learned correction; CTF_EUNSUPPORTED otherwise).  A solver step of
+ * every problem is recorded once as a list of operations; the launch keeps one wave of resident
+ * blocks that take work items (a chunk of tiles of one operation of one problem) from a device
+ * ticket counter in a fixed order (step, operation, problem, chunk), each item first waiting until
+ * the items of its problem ahead of it have finished.  A problem's update of its convergence flag
+ * runs on the device, and once converged its remaining items are skipped; the launch ends when
+ * every problem has converged or after max_steps steps of each.  Every wait is bounded (about 4 s):
+ * if one runs out, the launch ends and CTF_EHIP is returned.  Iterates, norms and step counts are
+ * those of ctf_solve_batch, bit for bit (the same per-element arithmetic and reduction orders).
+ * items_per_block (0: default 1): the largest operation of the batch is split into about that many
+ * work items per resident block (1 was the fastest measured; every item costs a device-wide
+ * release and acquire of memory).  workspace: device memory of ctf_solve_batch_persistent_bytes()
+ * bytes, 256-byte aligned, owned by the caller (the schedule and the counters; overwritten).  Runs
+ * on the first problem's stream and returns when the launch has finished; the problems' own
+ * streams must be idle.  Returns CTF_OK when all converged, CTF_NOT_CONVERGED otherwise. */
+int ctf_solve_batch_persistent(ctf_problem* const* probs, int nprob, double* const* psis, double rtol,
+                               int max_steps, int items_per_block, void* workspace, size_t ws_bytes,
+                               ctf_solve_info* infos);
+/* Workspace bytes of ctf_solve_batch_persistent for these problems on the current device (0 on a
+ * bad argument, an unsupported problem or no device). */
+size_t ctf_solve_batch_persistent_bytes(ctf_problem* const* probs, int nprob, int items_per_block);
+
 /* Launch shape of the finest-level kernels: rows per wavefront strip of the ConvFEM/PG kernels
  * (8..512), the block size of the upwind correction sweeps (multiple of 64, <= 1024), and for
  * the non-linear PG whether the diffusivities are formed in the residual's own pass (pg_fused = 1)

@@ -9,6 +9,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdint>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1343,6 +1344,106 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
   }
   cleanup();
   return status;
+}
+
+namespace {
+// One solver step of every problem recorded as a tape of operations (the launches step_async makes,
+// not launched); the problems' timers are off while recording.
+struct TapeSet {
+  std::vector<PersistTape*> tapes;
+  ~TapeSet() {
+    for (PersistTape* t : tapes) tape_free(t);
+  }
+};
+
+int record_steps(ctf_problem* const* probs, int nprob, double* const* psis, double rtol, TapeSet* ts) {
+  for (int i = 0; i < nprob; ++i) {
+    ctf_problem* P = probs[i];
+    if (P->cfg.discretisation != CTF_UPWIND || P->cfg.coupled_scatter || P->cnn_on)
+      return fail(CTF_EUNSUPPORTED, "the persistent batch runs the upwind discretisation without scattering-coupled "
+                                    "sweeps or the learned correction");
+    const bool timing = P->timing;
+    P->timing = false;
+    ts->tapes.push_back(tape_open());
+    const int rc = step_async(P, psis ? psis[i] : nullptr, rtol);
+    tape_close();
+    P->timing = timing;
+    if (rc != CTF_OK) return rc;
+    if (!tape_usable(ts->tapes.back())) return fail(CTF_EUNSUPPORTED, "a step of this problem cannot be recorded");
+  }
+  return CTF_OK;
+}
+
+int persist_items_per_block(int v) { return v > 0 ? v : 1; }
+constexpr unsigned kPersistSpinLimit = 1u << 21;   // polls (about 2 us each) of one bounded wait
+}  // namespace
+
+size_t ctf_solve_batch_persistent_bytes(ctf_problem* const* probs, int nprob, int items_per_block) {
+  if (!probs || nprob < 1 || items_per_block < 0) return 0;
+  for (int i = 0; i < nprob; ++i)
+    if (!probs[i]) return 0;
+  TapeSet ts;
+  if (record_steps(probs, nprob, nullptr, 0.0, &ts) != CTF_OK) return 0;
+  int blocks = 0;
+  if (persist_grid(&blocks) != hipSuccess) return 0;
+  return persist_workspace_bytes(ts.tapes.data(), nprob, blocks, persist_items_per_block(items_per_block));
+}
+
+int ctf_solve_batch_persistent(ctf_problem* const* probs, int nprob, double* const* psis, double rtol, int max_steps,
+                               int items_per_block, void* workspace, size_t ws_bytes, ctf_solve_info* infos) {
+  if (!probs || !psis || nprob < 1 || max_steps < 1 || items_per_block < 0) return fail(CTF_EINVAL, "bad argument");
+  for (int i = 0; i < nprob; ++i) {
+    if (!probs[i] || !psis[i]) return fail(CTF_EINVAL, "null problem or psi");
+    for (int j = 0; j < i; ++j)
+      if (probs[j] == probs[i]) return fail(CTF_EINVAL, "a problem appears twice in the batch");
+  }
+  const auto t0 = std::chrono::steady_clock::now();
+  TapeSet ts;
+  int rc = record_steps(probs, nprob, psis, rtol, &ts);
+  if (rc != CTF_OK) return rc;
+  int blocks = 0;
+  CTF_HIP(persist_grid(&blocks));
+  const int ipb = persist_items_per_block(items_per_block);
+  const size_t need = persist_workspace_bytes(ts.tapes.data(), nprob, blocks, ipb);
+  if (!workspace || ws_bytes < need) return fail(CTF_ENOMEM, "workspace too small for the persistent batch");
+  if (reinterpret_cast<uintptr_t>(workspace) & 255) return fail(CTF_EINVAL, "workspace must be 256-byte aligned");
+  // every problem restarts active with its step counter at zero; all prior work finished
+  for (int i = 0; i < nprob; ++i) {
+    ctf_problem* P = probs[i];
+    CTF_HIP(launch_set_int(P->active, 1, P->stream));
+    CTF_HIP(hipMemsetAsync(P->scal, 0, 8 * sizeof(double), P->stream));
+    CTF_HIP(hipStreamSynchronize(P->stream));
+  }
+  PersistResult res;
+  CTF_HIP(persist_solve(ts.tapes.data(), nprob, max_steps, blocks, ipb, kPersistSpinLimit, workspace, ws_bytes,
+                        probs[0]->stream, &res));
+  std::vector<double> host(3 * size_t(nprob));
+  std::vector<int> act(nprob, 1);
+  for (int i = 0; i < nprob; ++i) {
+    CTF_HIP(hipMemcpyAsync(&host[3 * i], probs[i]->scal, 3 * sizeof(double), hipMemcpyDeviceToHost,
+                           probs[0]->stream));
+    CTF_HIP(hipMemcpyAsync(&act[i], probs[i]->active, sizeof(int), hipMemcpyDeviceToHost, probs[0]->stream));
+  }
+  CTF_HIP(hipStreamSynchronize(probs[0]->stream));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  bool any = false;
+  for (int i = 0; i < nprob; ++i) {
+    any = any || act[i];
+    if (infos) {
+      const int steps = int(host[3 * i + 2]);
+      const bool mixed = probs[i]->mixed();
+      infos[i].cycles = mixed ? steps * probs[i]->cfg.n_inner : steps;
+      infos[i].outer_steps = mixed ? steps : 0;
+      infos[i].rel_residual = host[3 * i + 1];
+      infos[i].seconds = secs;
+      infos[i].cnn_applied = 0;
+      infos[i].cnn_rejected = 0;
+    }
+  }
+  if (res.error == kPersistNonFinite) return fail(CTF_ENONFINITE, "non-finite residual norm in the batch");
+  if (res.error == kPersistSpin)
+    return fail(CTF_EHIP, "a bounded wait of the persistent batch ran out (were all its blocks resident?)");
+  return any ? CTF_NOT_CONVERGED : CTF_OK;
 }
 
 int ctf_set_launch_shape(ctf_problem* P, int strip_h, int corr_block, int pg_fused) {

@@ -201,6 +201,34 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
 hipError_t launch_add_diff_f2d(double* y, const float* u, size_t n, hipStream_t s,
                                const int* active = nullptr);
 
+// ---- persistent batched solve (kernels.hip) ------------------------------------------------------
+// While a tape is open on the calling thread, the launchers of the upwind solve path (moments,
+// emission, upwind operator, sweeps, restriction, norm sums, activity update, copies) append their
+// work to it instead of launching; any other launcher fails with hipErrorNotSupported and marks
+// the tape unusable.
+struct PersistTape;
+PersistTape* tape_open();
+void tape_close();
+void tape_free(PersistTape* t);
+// recorded without a refused launch, with an activity update and at least one operation
+bool tape_usable(const PersistTape* t);
+
+enum PersistError : int { kPersistSpin = 1, kPersistNonFinite = 2 };
+struct PersistResult {
+  unsigned long long tickets = 0;      // work items handed out (including ones fetched at exit)
+  unsigned long long round_items = 0;  // work items of one step of every problem
+  int n_active = 0;                    // problems not converged when the launch ended
+  int error = 0;                       // 0, kPersistSpin (a bounded wait ran out) or kPersistNonFinite
+  int blocks = 0;
+};
+// resident blocks of the persistent kernel on the current device (its grid)
+hipError_t persist_grid(int* blocks);
+size_t persist_workspace_bytes(const PersistTape* const* tapes, int nprob, int blocks, int items_per_block);
+// Runs up to max_steps steps of every taped problem in one launch on s and waits for it.  Each
+// problem's flags must be set (active = 1) and its step counters cleared beforehand.
+hipError_t persist_solve(const PersistTape* const* tapes, int nprob, int max_steps, int blocks, int items_per_block,
+                         unsigned spin_limit, void* ws, size_t ws_bytes, hipStream_t s, PersistResult* res);
+
 // ---- learned coarse-grid correction (cnn.hip) ---------------------------------------------------
 int cnn_param_count();
 size_t cnn_workspace_bytes(int B, int H, int W);

@@ -3,6 +3,10 @@
 // Layout of every angular-flux-shaped array: [G][n_dir][n][n], x fastest; 64-bit offsets.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+
 #include "internal.h"
 
 namespace ctf {
@@ -12,6 +16,15 @@ namespace {
 constexpr int kBlock = 256;
 
 __device__ __forceinline__ bool idle(const int* active) { return active && *active == 0; }
+
+// A block's place in its grid: the hardware's for a kernel launched on its own, or one tile of an
+// operation run by the persistent batched kernel (bd: threads per block).
+struct VBlk {
+  unsigned x, y, z, gx, gy, gz, bd;
+};
+__device__ __forceinline__ VBlk hw_blk() {
+  return VBlk{blockIdx.x, blockIdx.y, blockIdx.z, gridDim.x, gridDim.y, gridDim.z, blockDim.x};
+}
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -159,13 +172,13 @@ __device__ __forceinline__ bool halo_zero(int gi, int gj, int n, T mu, T nu, int
 constexpr int kMomCells = 64;
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __restrict__ psi,
+__device__ __forceinline__ void b_moments(const VBlk& vb, LevelData<T> L, const T* __restrict__ psi,
                                                      T* __restrict__ phi, int nmom) {
   if (idle(L.dims.active)) return;
   const int ncell = L.dims.n * L.dims.n;
   const int lane = threadIdx.x % kMomCells, q = threadIdx.x / kMomCells;
-  const int cell = blockIdx.x * kMomCells + lane;
-  const int g = blockIdx.y;
+  const int cell = vb.x * kMomCells + lane;
+  const int g = vb.y;
   const int nd = L.dims.nd, per = nd / 4;
   __shared__ T red[3][4][kMomCells];
   T a0 = 0, a1 = 0, a2 = 0;
@@ -212,6 +225,10 @@ __global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __r
       dst[size_t(m) * ncell] = (red[m][0][lane] + red[m][1][lane]) + (red[m][2][lane] + red[m][3][lane]);
   }
 }
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_moments(LevelData<T> L, const T* __restrict__ psi, T* __restrict__ phi, int nmom) {
+  b_moments<T>(hw_blk(), L, psi, phi, nmom);
+}
 
 // BF16 MFMA form of the moment contraction (float32 psi in memory):
 //   Phi[m][cell] = sum_n W[m][n] psi[n][cell],  W = (w, w mu, w nu),
@@ -234,13 +251,13 @@ __device__ __forceinline__ float bf16_to_float(unsigned short b) {
   return __uint_as_float(static_cast<unsigned int>(b) << 16);
 }
 
-__global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, const float* __restrict__ psi,
+__device__ __forceinline__ void b_moments_mfma(const VBlk& vb, LevelData<float> L, const float* __restrict__ psi,
                                                           float* __restrict__ phi, int nmom) {
   if (idle(L.dims.active)) return;
   const int ncell = L.dims.n * L.dims.n;
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
-  const int c0 = blockIdx.x * 64;
-  const int g = blockIdx.y;
+  const int c0 = vb.x * 64;
+  const int g = vb.y;
   const int nd = L.dims.nd;
   const int per = nd / 4;                     // ordinates of this wave (a multiple of 2 at least)
   const int i = lane % 16, kq = lane / 16;    // A row / B column, and the K eighth-block of the lane
@@ -291,19 +308,22 @@ __global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, con
             (red[0][m][lane] + red[1][m][lane]) + (red[2][m][lane] + red[3][m][lane]);
   }
 }
+__global__ __launch_bounds__(kBlock) void k_moments_mfma(LevelData<float> L, const float* __restrict__ psi, float* __restrict__ phi, int nmom) {
+  b_moments_mfma(hw_blk(), L, psi, phi, nmom);
+}
 
 // emission E[g][m][cell]: q_n = E0 + mu_n E1 + nu_n E2, all divided by 4 pi
 template <typename T>
 // phi_coarse: phi is given on the grid of half the size (the moments of UpSamp(e) are those of e
 // on its own level, copied to the 2 x 2 children), read at the parent cell.
-__global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __restrict__ phi,
+__device__ __forceinline__ void b_emission(const VBlk& vb, LevelDims d, const T* __restrict__ phi,
                                                       const T* __restrict__ ss, int nl,
                                                       const T* __restrict__ src, T* __restrict__ E,
                                                       int phi_coarse) {
   if (idle(d.active)) return;
   const size_t ncell = size_t(d.n) * d.n;
-  const size_t t = size_t(blockIdx.x) * kBlock + threadIdx.x;
-  const int g = blockIdx.y, G = d.G;
+  const size_t t = size_t(vb.x) * kBlock + threadIdx.x;
+  const int g = vb.y, G = d.G;
   if (t >= ncell) return;
   size_t tp = t, np = ncell;
   if (phi_coarse) {
@@ -329,6 +349,10 @@ __global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __res
     dst[ncell] = T(3) * e1 * inv4pi;
     dst[2 * ncell] = T(3) * e2 * inv4pi;
   }
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_emission(LevelDims d, const T* __restrict__ phi, const T* __restrict__ ss, int nl, const T* __restrict__ src, T* __restrict__ E, int phi_coarse) {
+  b_emission<T>(hw_blk(), d, phi, ss, nl, src, E, phi_coarse);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1121,7 +1145,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
 constexpr int kCorrRows = 8;
 constexpr int kFullBlock = 256;
 template <typename T, int K>
-__global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int bc_vac,
+__device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, int bc_vac,
                                                             const T* __restrict__ psi,
                                                             const T* __restrict__ E, int nmomE,
                                                             T* __restrict__ out, float* __restrict__ out_f,
@@ -1130,10 +1154,10 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const int ntx = (n + 63) >> 6;
-  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
+  const int tx = int(vb.x) % ntx, ty = int(vb.x) / ntx;
   const int i = tx * 64 + int(threadIdx.x & 63);
   const int jb = (ty * (kFullBlock / 64) + int(threadIdx.x >> 6)) * kCorrRows;
-  const int d0 = int(blockIdx.y) * K, g = blockIdx.z;
+  const int d0 = int(vb.y) * K, g = vb.z;
   const size_t ncell = size_t(n) * n;
   double acc = 0.0;   // sum over the block's ordinates of w_n (sign rho)^2
   if (i < n && jb < n) {
@@ -1226,10 +1250,14 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const size_t b = blockIdx.x + size_t(gridDim.x) * (blockIdx.y + size_t(gridDim.y) * blockIdx.z);
+      const size_t b = vb.x + size_t(vb.gx) * (vb.y + size_t(vb.gy) * vb.z);
       partial[b] = red[0] * L.dims.h * L.dims.h;
     }
   }
+}
+template <typename T, int K>
+__global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int bc_vac, const T* __restrict__ psi, const T* __restrict__ E, int nmomE, T* __restrict__ out, float* __restrict__ out_f, int mode, T sign, const T* __restrict__ rhs, double* __restrict__ partial) {
+  b_upwind_full<T, K>(hw_blk(), L, bc_vac, psi, E, nmomE, out, out_f, mode, sign, rhs, partial);
 }
 
 // correction sweep on one level: e_new = e + (rhs - A_up e - sigma_t e) / d
@@ -1239,7 +1267,7 @@ __global__ __launch_bounds__(kFullBlock) void k_upwind_full(LevelData<T> L, int 
 // it read one row before (every e value is loaded once for the centre and once, from cache, as an
 // x neighbour).  With acc the new value is added to acc instead of being written to xout.
 template <typename T, int XMODE, bool SCAT>
-__global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac,
+__device__ __forceinline__ void b_upwind_corr(const VBlk& vb, LevelData<T> L, int bc_vac,
                                                          const T* __restrict__ xin, int ndc,
                                                          const T* __restrict__ rhs,
                                                          T* __restrict__ xout, T* __restrict__ acc,
@@ -1247,12 +1275,12 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const int ntx = (n + 63) >> 6;
-  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
+  const int tx = int(vb.x) % ntx, ty = int(vb.x) / ntx;
   const int i = tx * 64 + int(threadIdx.x & 63);
-  const int jb = (ty * int(blockDim.x >> 6) + int(threadIdx.x >> 6)) * kCorrRows;
+  const int jb = (ty * int(vb.bd >> 6) + int(threadIdx.x >> 6)) * kCorrRows;
   if (i >= n || jb >= n) return;
   const int je = min(jb + kCorrRows, n);
-  const int dir = blockIdx.y, g = blockIdx.z;
+  const int dir = vb.y, g = vb.z;
   const size_t ncell = size_t(n) * n;
   const size_t plane = (size_t(g) * nd + dir) * ncell;
   const T mu = L.mu[dir], nu = L.nu[dir], h = T(L.dims.h);
@@ -1316,6 +1344,10 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
     eprev = c;
   }
 }
+template <typename T, int XMODE, bool SCAT>
+__global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac, const T* __restrict__ xin, int ndc, const T* __restrict__ rhs, T* __restrict__ xout, T* __restrict__ acc, const T* __restrict__ E, int nmomE) {
+  b_upwind_corr<T, XMODE, SCAT>(hw_blk(), L, bc_vac, xin, ndc, rhs, xout, acc, E, nmomE);
+}
 
 // Two correction sweeps in one pass: e1 = S(e0), e2 = S(e1), S the sweep above without the
 // scattering term.  Besides e1 on its own column, each thread forms e1 on the upwind x neighbour
@@ -1323,19 +1355,19 @@ __global__ __launch_bounds__(1024) void k_upwind_corr(LevelData<T> L, int bc_vac
 // row, so that no intermediate value crosses threads and e1 never goes to memory.  The arithmetic
 // of every value is that of the single sweep.  R rows per thread.
 template <typename T, int XMODE, int R, int K>
-__global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<T> L, int bc_vac,
+__device__ __forceinline__ void b_upwind_corr2(const VBlk& vb, LevelData<T> L, int bc_vac,
                                                           const T* __restrict__ xin, int ndc,
                                                           const T* __restrict__ rhs,
                                                           T* __restrict__ xout, T* __restrict__ acc) {
   if (idle(L.dims.active)) return;
   const int n = L.dims.n, nd = L.dims.nd;
   const int ntx = (n + 63) >> 6;
-  const int tx = int(blockIdx.x) % ntx, ty = int(blockIdx.x) / ntx;
+  const int tx = int(vb.x) % ntx, ty = int(vb.x) / ntx;
   const int i = tx * 64 + int(threadIdx.x & 63);
-  const int jb = (ty * int(blockDim.x >> 6) + int(threadIdx.x >> 6)) * R;
+  const int jb = (ty * int(vb.bd >> 6) + int(threadIdx.x >> 6)) * R;
   if (i >= n || jb >= n) return;
   const int je = min(jb + R, n);
-  const int d0 = int(blockIdx.y) * K, g = blockIdx.z;
+  const int d0 = int(vb.y) * K, g = vb.z;
   const size_t ncell = size_t(n) * n;
   const T h = T(L.dims.h);
   const T mu0 = L.mu[d0], nu0 = L.nu[d0];   // signs shared by the K ordinates of the block
@@ -1425,18 +1457,22 @@ __global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<
     }
   }
 }
+template <typename T, int XMODE, int R, int K>
+__global__ __launch_bounds__(K == 1 ? 1024 : 256) void k_upwind_corr2(LevelData<T> L, int bc_vac, const T* __restrict__ xin, int ndc, const T* __restrict__ rhs, T* __restrict__ xout, T* __restrict__ acc) {
+  b_upwind_corr2<T, XMODE, R, K>(hw_blk(), L, bc_vac, xin, ndc, rhs, xout, acc);
+}
 
 // restriction: coarse = sum_{child ordinates, 2x2 cells} w_n rho h^2 / (w_N H^2)
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<T> Lc,
+__device__ __forceinline__ void b_restrict(const VBlk& vb, LevelData<T> Lf, LevelData<T> Lc,
                                                       const T* __restrict__ fine,
                                                       T* __restrict__ coarse) {
   if (idle(Lf.dims.active)) return;
   const int nc = Lc.dims.n, ndc = Lc.dims.nd, nf = Lf.dims.n, naf = Lf.dims.na;
   const size_t nccell = size_t(nc) * nc, nfcell = size_t(nf) * nf;
-  const int cell = int(blockIdx.x) * kBlock + int(threadIdx.x);
+  const int cell = int(vb.x) * kBlock + int(threadIdx.x);
   if (cell >= int(nccell)) return;
-  const int N = blockIdx.y, g = blockIdx.z;
+  const int N = vb.y, g = vb.z;
   const size_t idx = (size_t(g) * ndc + N) * nccell + cell;
   const int J = cell / nc, I = cell - J * nc;
   int kids[4], nk = 0;
@@ -1455,6 +1491,10 @@ __global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<
   }
   const T hf = T(Lf.dims.h), hc = T(Lc.dims.h);
   coarse[idx] = s * (hf * hf) / (Lc.w[N] * (hc * hc));
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_restrict(LevelData<T> Lf, LevelData<T> Lc, const T* __restrict__ fine, T* __restrict__ coarse) {
+  b_restrict<T>(hw_blk(), Lf, Lc, fine, coarse);
 }
 
 template <typename T>
@@ -1499,7 +1539,7 @@ __global__ __launch_bounds__(kBlock) void k_wnorm2_partial(LevelData<T> L, const
   if (threadIdx.x == 0) partial[blockIdx.x] = red[0] * L.dims.h * L.dims.h;
 }
 
-__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partial, int np,
+__device__ __forceinline__ void b_sum_partials(const VBlk& vb, const double* __restrict__ partial, int np,
                                                           double* __restrict__ out, const int* active) {
   if (idle(active)) return;
   __shared__ double red[kBlock];
@@ -1513,15 +1553,18 @@ __global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restric
   }
   if (threadIdx.x == 0) out[0] = red[0];
 }
+__global__ __launch_bounds__(kBlock) void k_sum_partials(const double* __restrict__ partial, int np, double* __restrict__ out, const int* active) {
+  b_sum_partials(hw_blk(), partial, np, out, active);
+}
 
 // first stage of a long sum: block b adds the b-th of kSumBlocks contiguous chunks (fixed order)
 constexpr int kSumBlocks = 256;
-__global__ __launch_bounds__(kBlock) void k_sum_chunks(const double* __restrict__ partial, int np,
+__device__ __forceinline__ void b_sum_chunks(const VBlk& vb, const double* __restrict__ partial, int np,
                                                         double* __restrict__ stage, const int* active) {
   if (idle(active)) return;
   __shared__ double red[kBlock];
   const int chunk = (np + kSumBlocks - 1) / kSumBlocks;
-  const int beg = int(blockIdx.x) * chunk, end = min(beg + chunk, np);
+  const int beg = int(vb.x) * chunk, end = min(beg + chunk, np);
   double acc = 0.0;
   for (int i = beg + int(threadIdx.x); i < end; i += kBlock) acc += partial[i];
   red[threadIdx.x] = acc;
@@ -1530,7 +1573,10 @@ __global__ __launch_bounds__(kBlock) void k_sum_chunks(const double* __restrict_
     if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) stage[blockIdx.x] = red[0];
+  if (threadIdx.x == 0) stage[vb.x] = red[0];
+}
+__global__ __launch_bounds__(kBlock) void k_sum_chunks(const double* __restrict__ partial, int np, double* __restrict__ stage, const int* active) {
+  b_sum_chunks(hw_blk(), partial, np, stage, active);
 }
 
 template <typename T>
@@ -1566,11 +1612,14 @@ __global__ __launch_bounds__(kBlock) void k_f2d(const float* __restrict__ in, do
   const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
   if (i < n) out[i] = double(in[i]);
 }
-__global__ __launch_bounds__(kBlock) void k_add_f2d(double* __restrict__ y, const float* __restrict__ x,
+__device__ __forceinline__ void b_add_f2d(const VBlk& vb, double* __restrict__ y, const float* __restrict__ x,
                                                      size_t n, const int* active) {
   if (idle(active)) return;
-  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  const size_t i = size_t(vb.x) * kBlock + threadIdx.x;
   if (i < n) y[i] += double(x[i]);
+}
+__global__ __launch_bounds__(kBlock) void k_add_f2d(double* __restrict__ y, const float* __restrict__ x, size_t n, const int* active) {
+  b_add_f2d(hw_blk(), y, x, n, active);
 }
 
 // y += u - fl32(y): the full-approximation update, with the float32 start value re-derived from y
@@ -1599,11 +1648,15 @@ __global__ void k_set_int(int* p, int v) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n,
+__device__ __forceinline__ void b_copy(const VBlk& vb, T* __restrict__ dst, const T* __restrict__ src, size_t n,
                                                   const int* active) {
   if (idle(active)) return;
-  const size_t i = size_t(blockIdx.x) * kBlock + threadIdx.x;
+  const size_t i = size_t(vb.x) * kBlock + threadIdx.x;
   if (i < n) dst[i] = src[i];
+}
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_copy(T* __restrict__ dst, const T* __restrict__ src, size_t n, const int* active) {
+  b_copy<T>(hw_blk(), dst, src, n, active);
 }
 
 inline unsigned nblocks(size_t total) { return unsigned((total + kBlock - 1) / kBlock); }
@@ -1611,19 +1664,104 @@ inline unsigned nblocks(size_t total) { return unsigned((total + kBlock - 1) / k
 }  // namespace
 
 // ---------------------------------------------------------------------------------------------
+// Recording for the persistent batched solve.  While a tape is open on the calling thread, the
+// launchers of the upwind solve path append one operation (kind, template choice, grid and
+// arguments) to it instead of launching, and every other launcher fails with
+// hipErrorNotSupported.  Recorded arguments carry no activity flag: the persistent kernel skips
+// the operations of a converged problem itself.  Sweeps are recorded at 256 threads per block
+// (the block shape changes no arithmetic).
+enum PKind : int { P_MOM, P_MOM_MFMA, P_EMIS, P_UPF, P_CORR, P_CORR2, P_RESTRICT, P_SUMCH, P_SUMP, P_ACTIVE,
+                   P_COPY, P_ADDF2D };
+
+template <typename T> struct AMom { LevelData<T> L; const T* psi; T* phi; int nmom; };
+template <typename T> struct AEmis { LevelDims d; const T* phi; const T* ss; int nl; const T* src; T* E; int coarse; };
+template <typename T> struct AUpf {
+  LevelData<T> L; int bc_vac; const T* psi; const T* E; int nmomE; T* out; float* out_f; int mode; T sign;
+  const T* rhs; double* partial;
+};
+template <typename T> struct ACorr { LevelData<T> L; int bc_vac; const T* xin; int ndc; const T* rhs; T* xout; T* acc; };
+template <typename T> struct ARestrict { LevelData<T> Lf, Lc; const T* fine; T* coarse; };
+struct ASum { const double* partial; int np; double* out; };
+struct AActive { const double* norm2; double bnorm, rtol; double* rel; int* active; double* steps; };
+template <typename T> struct ACopy { T* dst; const T* src; size_t n; };
+struct AAddF2D { double* y; const float* x; size_t n; };
+
+constexpr int kOpArgBytes = 176;
+struct alignas(16) POp {
+  int kind, fp64, xmode, kb;       // kb: ordinates per block of the upwind operator / paired sweep
+  unsigned gx, gy, gz, tiles;      // the operation's grid; a tile is one block of it
+  unsigned chunk, items;           // tiles per work item, work items
+  unsigned long long before;       // work items of the problem's step ahead of this operation
+  unsigned char arg[kOpArgBytes];  // one of the argument structs above
+};
+
+}  // namespace ctf
+
+struct ctf::PersistTape {
+  std::vector<POp> ops;
+  int* active = nullptr;  // the problem's activity flag (argument of its update operation)
+  bool bad = false;       // a launcher that cannot be recorded was called
+};
+
+namespace ctf {
+
+namespace {
+thread_local PersistTape* g_tape = nullptr;
+
+template <typename A>
+hipError_t tape_add(int kind, int fp64, int xmode, int kb, dim3 grid, const A& a) {
+  static_assert(sizeof(A) <= kOpArgBytes, "operation arguments too large");
+  static_assert(std::is_trivially_copyable<A>::value, "operation arguments must be plain data");
+  POp op{};
+  op.kind = kind;
+  op.fp64 = fp64;
+  op.xmode = xmode;
+  op.kb = kb;
+  op.gx = grid.x;
+  op.gy = grid.y;
+  op.gz = grid.z;
+  op.tiles = grid.x * grid.y * grid.z;
+  std::memcpy(op.arg, &a, sizeof(A));
+  g_tape->ops.push_back(op);
+  return hipSuccess;
+}
+
+hipError_t tape_refuse() {
+  g_tape->bad = true;
+  return hipErrorNotSupported;
+}
+
+template <typename T>
+LevelData<T> no_flag(LevelData<T> L) {
+  L.dims.active = nullptr;
+  return L;
+}
+}  // namespace
+
+PersistTape* tape_open() {
+  g_tape = new PersistTape();
+  return g_tape;
+}
+void tape_close() { g_tape = nullptr; }
+void tape_free(PersistTape* t) { delete t; }
+bool tape_usable(const PersistTape* t) { return t && !t->bad && t->active && !t->ops.empty(); }
+
+// ---------------------------------------------------------------------------------------------
 template <typename T>
 hipError_t launch_moments(const LevelData<T>& L, const T* psi, T* phi, int nmom, hipStream_t s) {
   const int ncell = L.dims.n * L.dims.n;
-  hipLaunchKernelGGL(k_moments<T>, dim3((ncell + kMomCells - 1) / kMomCells, L.dims.G), dim3(kBlock),
-                     0, s, L, psi, phi, nmom);
+  const dim3 grid((ncell + kMomCells - 1) / kMomCells, L.dims.G);
+  if (g_tape) return tape_add(P_MOM, sizeof(T) == 8, 0, 0, grid, AMom<T>{no_flag(L), psi, phi, nmom});
+  hipLaunchKernelGGL(k_moments<T>, grid, dim3(kBlock), 0, s, L, psi, phi, nmom);
   return hipGetLastError();
 }
 
 hipError_t launch_moments_mfma(const LevelData<float>& L, const float* psi, float* phi, int nmom,
                                hipStream_t s) {
   const int ncell = L.dims.n * L.dims.n;
-  hipLaunchKernelGGL(k_moments_mfma, dim3((ncell + 63) / 64, L.dims.G), dim3(kBlock), 0, s, L, psi,
-                     phi, nmom);
+  const dim3 grid((ncell + 63) / 64, L.dims.G);
+  if (g_tape) return tape_add(P_MOM_MFMA, 0, 0, 0, grid, AMom<float>{no_flag(L), psi, phi, nmom});
+  hipLaunchKernelGGL(k_moments_mfma, grid, dim3(kBlock), 0, s, L, psi, phi, nmom);
   return hipGetLastError();
 }
 
@@ -1631,8 +1769,13 @@ template <typename T>
 hipError_t launch_emission(const LevelDims& d, const T* phi, const T* ss, int nl, const T* src,
                            T* E, hipStream_t s, int phi_coarse) {
   const size_t ncell = size_t(d.n) * d.n;
-  hipLaunchKernelGGL(k_emission<T>, dim3(nblocks(ncell), d.G), dim3(kBlock), 0, s, d, phi, ss, nl,
-                     src, E, phi_coarse);
+  const dim3 grid(nblocks(ncell), d.G);
+  if (g_tape) {
+    LevelDims dn = d;
+    dn.active = nullptr;
+    return tape_add(P_EMIS, sizeof(T) == 8, 0, 0, grid, AEmis<T>{dn, phi, ss, nl, src, E, phi_coarse});
+  }
+  hipLaunchKernelGGL(k_emission<T>, grid, dim3(kBlock), 0, s, d, phi, ss, nl, src, E, phi_coarse);
   return hipGetLastError();
 }
 
@@ -1668,6 +1811,7 @@ PGArgs<T> pg_args(const LevelData<T>& L, const Stencils<T>& st, const PGParams& 
 template <typename T>
 hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
                                  const PGLaunch<T>& o, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   if (!o.kx_out || !o.ky_out) return hipErrorInvalidValue;
   PGArgs<T> a = pg_args(L, st, pp, o);
   a.kx_out = o.kx_out;
@@ -1702,6 +1846,7 @@ hipError_t launch_pg_diffusivity(int p, const LevelData<T>& L, const Stencils<T>
 template <typename T>
 hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const PGParams& pp,
                      const PGLaunch<T>& o, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   if (sizeof(T) == 4 && o.partial) return hipErrorInvalidValue;   // the float32 kernels form no norms
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
@@ -1798,6 +1943,9 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
   if (mode == 0 && !out && !out_f) return hipErrorInvalidValue;
   if (L.dims.nd % per_face) return hipErrorInvalidValue;
   if (npartial) *npartial = int(blocks);
+  if (g_tape)
+    return tape_add(P_UPF, sizeof(T) == 8, 0, kb, grid,
+                    AUpf<T>{no_flag(L), bc_vac, psi, E, nmomE, out, out_f, mode, sign, rhs, partial});
   if (kb == 4)
     hipLaunchKernelGGL((k_upwind_full<T, 4>), grid, dim3(kFullBlock), 0, s, L, bc_vac, psi, E, nmomE, out, out_f,
                        mode, sign, rhs, partial);
@@ -1811,11 +1959,18 @@ template <typename T>
 hipError_t launch_upwind_correction(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode,
                                     int ndc, const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block,
                                     const T* E, int nmomE) {
+  if (g_tape) {
+    if (E) return tape_refuse();   // the scattering-coupled sweep is not recorded
+    block = kBlock;
+  }
   if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
   const int n = L.dims.n;
   const int rows_per_block = (block / 64) * kCorrRows;
   const unsigned nb = unsigned((n + 63) / 64) * unsigned((n + rows_per_block - 1) / rows_per_block);
   const dim3 grid(nb, L.dims.nd, L.dims.G), blk(block);
+  if (g_tape)
+    return tape_add(P_CORR, sizeof(T) == 8, xmode, 1, grid,
+                    ACorr<T>{no_flag(L), bc_vac, x_in, ndc, rhs, x_out, psi_acc});
 #define CTF_CORR(X, S) hipLaunchKernelGGL((k_upwind_corr<T, X, S>), grid, blk, 0, s, L, bc_vac, x_in, ndc, rhs, \
                                           x_out, psi_acc, E, nmomE)
   if (E) {
@@ -1837,6 +1992,7 @@ template <typename T> constexpr int corr2_rows() { return sizeof(T) == 8 ? 4 : 8
 template <typename T>
 hipError_t launch_upwind_correction2(const LevelData<T>& L, int bc_vac, const T* x_in, int xmode, int ndc,
                                      const T* rhs, T* x_out, T* psi_acc, hipStream_t s, int block) {
+  if (g_tape) block = kBlock;
   if (block < 64 || block > 1024 || block % 64) return hipErrorInvalidValue;
   constexpr int R = corr2_rows<T>();
   const int n = L.dims.n;
@@ -1850,6 +2006,9 @@ hipError_t launch_upwind_correction2(const LevelData<T>& L, int bc_vac, const T*
   const int rows_pb = (block / 64) * R;
   const unsigned nb = unsigned((n + 63) / 64) * unsigned((n + rows_pb - 1) / rows_pb);
   const dim3 grid(nb, unsigned(L.dims.nd / kb), L.dims.G), blk(block);
+  if (g_tape)
+    return tape_add(P_CORR2, sizeof(T) == 8, xmode, kb, grid,
+                    ACorr<T>{no_flag(L), bc_vac, x_in, ndc, rhs, x_out, psi_acc});
 #define CTF_CORR2(X, KK) hipLaunchKernelGGL((k_upwind_corr2<T, X, R, KK>), grid, blk, 0, s, L, bc_vac, x_in, ndc, \
                                             rhs, x_out, psi_acc)
   if (kb == 4) {
@@ -1869,12 +2028,15 @@ template <typename T>
 hipError_t launch_restrict(const LevelData<T>& Lf, const LevelData<T>& Lc, const T* fine, T* coarse,
                            hipStream_t s) {
   const dim3 grid(nblocks(size_t(Lc.dims.n) * Lc.dims.n), Lc.dims.nd, Lc.dims.G);
+  if (g_tape)
+    return tape_add(P_RESTRICT, sizeof(T) == 8, 0, 0, grid, ARestrict<T>{no_flag(Lf), no_flag(Lc), fine, coarse});
   hipLaunchKernelGGL(k_restrict<T>, grid, dim3(kBlock), 0, s, Lf, Lc, fine, coarse);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_prolong(const LevelData<T>& Lf, int ndc, const T* coarse, T* fine, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   const dim3 grid(nblocks(size_t(Lf.dims.n) * Lf.dims.n), Lf.dims.nd, Lf.dims.G);
   hipLaunchKernelGGL(k_prolong<T>, grid, dim3(kBlock), 0, s, Lf, ndc, coarse, fine);
   return hipGetLastError();
@@ -1885,6 +2047,7 @@ int wnorm2_partials(const LevelDims&) { return kNormBlocks; }
 template <typename T>
 hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int npartial,
                          double* out, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_wnorm2_partial<T>, dim3(npartial), dim3(kBlock), 0, s, L, v, partial);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(kBlock), 0, s, partial, npartial, out, L.dims.active);
   return hipGetLastError();
@@ -1893,6 +2056,13 @@ hipError_t launch_wnorm2(const LevelData<T>& L, const T* v, double* partial, int
 int sum_partials_extra() { return kSumBlocks; }
 
 hipError_t launch_sum_partials(double* partial, int np, double* out, hipStream_t s, const int* active) {
+  if (g_tape) {
+    if (np > 16 * kBlock) {
+      (void)tape_add(P_SUMCH, 1, 0, 0, dim3(kSumBlocks), ASum{partial, np, partial + np});
+      return tape_add(P_SUMP, 1, 0, 0, dim3(1), ASum{partial + np, kSumBlocks, out});
+    }
+    return tape_add(P_SUMP, 1, 0, 0, dim3(1), ASum{partial, np, out});
+  }
   if (np > 16 * kBlock) {
     // two stages: kSumBlocks chunk sums after the np partials, then their sum
     double* stage = partial + np;
@@ -1906,17 +2076,24 @@ hipError_t launch_sum_partials(double* partial, int np, double* out, hipStream_t
 
 hipError_t launch_update_active(const double* norm2, double bnorm, double rtol, double* rel, int* active,
                                 double* steps, hipStream_t s) {
+  if (g_tape) {
+    if (g_tape->active && g_tape->active != active) return tape_refuse();
+    g_tape->active = active;
+    return tape_add(P_ACTIVE, 1, 0, 0, dim3(1), AActive{norm2, bnorm, rtol, rel, active, steps});
+  }
   hipLaunchKernelGGL(k_update_active, dim3(1), dim3(64), 0, s, norm2, bnorm, rtol, rel, active, steps);
   return hipGetLastError();
 }
 
 hipError_t launch_set_int(int* p, int v, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_set_int, dim3(1), dim3(64), 0, s, p, v);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_copy(T* dst, const T* src, size_t n, hipStream_t s, const int* active) {
+  if (g_tape) return tape_add(P_COPY, sizeof(T) == 8, 0, 0, dim3(nblocks(n)), ACopy<T>{dst, src, n});
   hipLaunchKernelGGL(k_copy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, dst, src, n, active);
   return hipGetLastError();
 }
@@ -1925,30 +2102,36 @@ template hipError_t launch_copy<float>(float*, const float*, size_t, hipStream_t
 
 template <typename T>
 hipError_t launch_axpy(T* y, const T* x, T a, size_t n, hipStream_t s, const int* active) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_axpy<T>, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, a, n, active);
   return hipGetLastError();
 }
 
 hipError_t launch_harmonic_coarsen(const double* fine, double* coarse, int G, int nc, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_harmonic, dim3(nblocks(size_t(nc) * nc * G)), dim3(kBlock), 0, s, fine,
                      coarse, G, nc);
   return hipGetLastError();
 }
 
 hipError_t launch_convert_d2f(const double* in, float* out, size_t n, hipStream_t s, const int* active) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_d2f, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n, active);
   return hipGetLastError();
 }
 hipError_t launch_convert_f2d(const float* in, double* out, size_t n, hipStream_t s) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, in, out, n);
   return hipGetLastError();
 }
 hipError_t launch_add_diff_f2d(double* y, const float* u, size_t n, hipStream_t s,
                                const int* active) {
+  if (g_tape) return tape_refuse();
   hipLaunchKernelGGL(k_add_diff_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, u, n, active);
   return hipGetLastError();
 }
 hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, const int* active) {
+  if (g_tape) return tape_add(P_ADDF2D, 1, 0, 0, dim3(nblocks(n)), AAddF2D{y, x, n});
   hipLaunchKernelGGL(k_add_f2d, dim3(nblocks(n)), dim3(kBlock), 0, s, y, x, n, active);
   return hipGetLastError();
 }
@@ -1977,5 +2160,369 @@ hipError_t launch_add_f2d(double* y, const float* x, size_t n, hipStream_t s, co
 
 CTF_INSTANTIATE(double)
 CTF_INSTANTIATE(float)
+
+// ---------------------------------------------------------------------------------------------
+// Persistent batched solve: one launch of k_persist runs up to max_steps solver steps of every
+// problem from their tapes.  Work items (a chunk of tiles of one operation) are handed out by a
+// ticket counter in a fixed order: round r (one step of every problem), then the operations in
+// tape order (slot s), then the problems, then the chunks.  An item of problem j first waits until
+// every item of j ahead of it has finished (done[j] counts j's finished items).  Tickets are taken
+// in order and an item waits only on items of smaller tickets, so the smallest unfinished ticket
+// can always run: with every block resident the launch cannot deadlock.  Items of a problem that
+// its update operation found converged are skipped.  Every wait is bounded: past spin_limit polls
+// the launch records an error and every block leaves.
+namespace {
+
+struct PSched {
+  const unsigned* op_begin;              // [nprob] first operation of problem j
+  const unsigned long long* step_items;  // [nprob] work items of one step of problem j
+  int* const* active;                    // [nprob] activity flags
+  const unsigned* item_slot;             // [round_items] slot k = s * nprob + j of each item of a round
+  const unsigned long long* slot_first;  // [n_slots * nprob] first item of slot k within a round
+  unsigned long long round_items, total_items;
+  unsigned nprob, spin_limit;
+  unsigned long long* ticket;
+  unsigned long long* done;              // [nprob]
+  int* n_active;
+  int* error;
+};
+
+template <typename A>
+__device__ __forceinline__ const A& oparg(const POp* o) {
+  return *reinterpret_cast<const A*>(o->arg);
+}
+template <typename V>
+__device__ __forceinline__ V ald(const V* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ void ast(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long aadd(unsigned long long* p, unsigned long long v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename T>
+__device__ __forceinline__ void run_typed(const POp* __restrict__ o, const VBlk& vb) {
+  constexpr int R = corr2_rows<T>();
+  switch (o->kind) {
+    case P_MOM: {
+      const auto& A = oparg<AMom<T>>(o);
+      b_moments<T>(vb, A.L, A.psi, A.phi, A.nmom);
+      break;
+    }
+    case P_EMIS: {
+      const auto& A = oparg<AEmis<T>>(o);
+      b_emission<T>(vb, A.d, A.phi, A.ss, A.nl, A.src, A.E, A.coarse);
+      break;
+    }
+    case P_UPF: {
+      const auto& A = oparg<AUpf<T>>(o);
+      if (o->kb == 4)
+        b_upwind_full<T, 4>(vb, A.L, A.bc_vac, A.psi, A.E, A.nmomE, A.out, A.out_f, A.mode, A.sign, A.rhs, A.partial);
+      else
+        b_upwind_full<T, 1>(vb, A.L, A.bc_vac, A.psi, A.E, A.nmomE, A.out, A.out_f, A.mode, A.sign, A.rhs, A.partial);
+      break;
+    }
+    case P_CORR: {
+      const auto& A = oparg<ACorr<T>>(o);
+      if (o->xmode == 0)
+        b_upwind_corr<T, 0, false>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc, nullptr, 1);
+      else if (o->xmode == 1)
+        b_upwind_corr<T, 1, false>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc, nullptr, 1);
+      else
+        b_upwind_corr<T, 2, false>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc, nullptr, 1);
+      break;
+    }
+    case P_CORR2: {
+      const auto& A = oparg<ACorr<T>>(o);
+      if (sizeof(T) == 8 && o->kb == 4) {   // the blocked form is recorded for float64 only
+        if (o->xmode == 0)
+          b_upwind_corr2<T, 0, R, 4>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+        else if (o->xmode == 1)
+          b_upwind_corr2<T, 1, R, 4>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+        else
+          b_upwind_corr2<T, 2, R, 4>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+      } else {
+        if (o->xmode == 0)
+          b_upwind_corr2<T, 0, R, 1>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+        else if (o->xmode == 1)
+          b_upwind_corr2<T, 1, R, 1>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+        else
+          b_upwind_corr2<T, 2, R, 1>(vb, A.L, A.bc_vac, A.xin, A.ndc, A.rhs, A.xout, A.acc);
+      }
+      break;
+    }
+    case P_RESTRICT: {
+      const auto& A = oparg<ARestrict<T>>(o);
+      b_restrict<T>(vb, A.Lf, A.Lc, A.fine, A.coarse);
+      break;
+    }
+    case P_COPY: {
+      const auto& A = oparg<ACopy<T>>(o);
+      b_copy<T>(vb, A.dst, A.src, A.n, nullptr);
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+__device__ __forceinline__ void run_op(const POp* __restrict__ o, const VBlk& vb) {
+  switch (o->kind) {
+    case P_MOM_MFMA: {
+      const auto& A = oparg<AMom<float>>(o);
+      b_moments_mfma(vb, A.L, A.psi, A.phi, A.nmom);
+      return;
+    }
+    case P_SUMCH: {
+      const auto& A = oparg<ASum>(o);
+      b_sum_chunks(vb, A.partial, A.np, A.out, nullptr);
+      return;
+    }
+    case P_SUMP: {
+      const auto& A = oparg<ASum>(o);
+      b_sum_partials(vb, A.partial, A.np, A.out, nullptr);
+      return;
+    }
+    case P_ADDF2D: {
+      const auto& A = oparg<AAddF2D>(o);
+      b_add_f2d(vb, A.y, A.x, A.n, nullptr);
+      return;
+    }
+    default:
+      break;
+  }
+  if (o->fp64) run_typed<double>(o, vb);
+  else run_typed<float>(o, vb);
+}
+
+// The update of the activity flag (one thread): rel = sqrt(norm2) / bnorm, active = rel > rtol,
+// steps += 1 while active, as the stand-alone update kernel does.  Values other blocks wrote in
+// this launch are read with atomic loads.
+__device__ void run_active(const POp* __restrict__ o, int* n_active, int* error) {
+  const auto& A = oparg<AActive>(o);
+  if (ald(A.active) == 0) return;
+  const double r = sqrt(ald(A.norm2)) / A.bnorm;
+  ast(A.rel, r);
+  const int on = (r > A.rtol || r != r) ? 1 : 0;
+  ast(A.active, on);
+  if (on) {
+    if (A.steps) ast(A.steps, ald(A.steps) + 1.0);
+  } else {
+    __hip_atomic_fetch_add(n_active, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!(r <= 1.7976931348623157e308)) ast(error, int(kPersistNonFinite));
+}
+
+__global__ __launch_bounds__(kBlock, 2) void k_persist(const POp* __restrict__ ops, PSched S) {
+  __shared__ int s_ctl;
+  __shared__ unsigned s_j, s_op, s_item;
+  unsigned long long t_next = 0;
+  if (threadIdx.x == 0) t_next = aadd(S.ticket, 1ull);
+  for (;;) {
+    if (threadIdx.x == 0) {
+      // ctl: 0 run the item, 1 skip it (problem converged), 2 leave, 3 the update ran here
+      const unsigned long long t = t_next;
+      int ctl = 0;
+      unsigned j = 0, opi = 0, item = 0;
+      if (t >= S.total_items || ald(S.error) != 0 || ald(S.n_active) == 0) {
+        ctl = 2;
+      } else {
+        t_next = aadd(S.ticket, 1ull);   // the next ticket, fetched while this item runs
+        const unsigned long long r = t / S.round_items, rem = t - r * S.round_items;
+        const unsigned k = S.item_slot[rem];
+        const unsigned slot = k / S.nprob;
+        j = k - slot * S.nprob;
+        item = unsigned(rem - S.slot_first[k]);
+        opi = S.op_begin[j] + slot;
+        const unsigned long long need = r * S.step_items[j] + ops[opi].before;
+        const int* act = S.active[j];
+        for (unsigned polls = 0;; ++polls) {
+          if (ald(act) == 0) {
+            ctl = 1;
+            break;
+          }
+          if (ald(S.done + j) >= need) break;
+          if (ald(S.error) != 0) {
+            ctl = 2;
+            break;
+          }
+          if (polls >= S.spin_limit) {
+            ast(S.error, int(kPersistSpin));
+            ctl = 2;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        if (ctl == 0) {
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+          if (ops[opi].kind == P_ACTIVE) {
+            run_active(ops + opi, S.n_active, S.error);
+            ctl = 3;
+          }
+        }
+      }
+      s_ctl = ctl;
+      s_j = j;
+      s_op = opi;
+      s_item = item;
+    }
+    __syncthreads();
+    const int ctl = __builtin_amdgcn_readfirstlane(s_ctl);
+    const unsigned j = __builtin_amdgcn_readfirstlane(s_j);
+    const unsigned opi = __builtin_amdgcn_readfirstlane(s_op);
+    const unsigned item = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (ctl == 2) return;
+    if (ctl == 0) {
+      const POp* __restrict__ o = ops + opi;
+      const unsigned gx = o->gx, gy = o->gy, gz = o->gz;
+      const unsigned t0 = item * o->chunk, t1 = min(t0 + o->chunk, o->tiles);
+      for (unsigned tile = t0; tile < t1; ++tile) {
+        const VBlk vb{tile % gx, (tile / gx) % gy, tile / (gx * gy), gx, gy, gz, unsigned(kBlock)};
+        run_op(o, vb);
+        __syncthreads();   // the operations' LDS is reused by the next tile
+      }
+    }
+    if (ctl == 0 || ctl == 3) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __syncthreads();
+      if (threadIdx.x == 0) aadd(S.done + j, 1ull);
+    }
+  }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+hipError_t persist_grid(int* blocks) {
+  int dev = 0, cus = 0, occ = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_persist, kBlock, 0);
+  if (e != hipSuccess) return e;
+  if (cus < 1 || occ < 1) return hipErrorInvalidConfiguration;
+  *blocks = cus * occ;
+  return hipSuccess;
+}
+
+namespace {
+// The schedule of a batch: chunk sizes and item counts of every operation, the slot table and the
+// workspace layout.  items_per_block: work items per resident block that one operation of the
+// largest problem is split into.
+struct PersistPlan {
+  std::vector<POp> ops;
+  std::vector<unsigned> op_begin;
+  std::vector<unsigned long long> step_items, slot_first;
+  std::vector<unsigned> item_slot;
+  unsigned long long round_items = 0;
+  size_t off_done = 0, off_active = 0, off_begin = 0, off_step = 0, off_ops = 0, off_first = 0, off_slot = 0,
+         bytes = 0;
+};
+
+PersistPlan plan_persist(const PersistTape* const* tapes, int nprob, int blocks, int items_per_block) {
+  PersistPlan pl;
+  size_t n_slots = 0;
+  const unsigned long long target = (unsigned long long)blocks * unsigned(std::max(1, items_per_block));
+  for (int j = 0; j < nprob; ++j) {
+    pl.op_begin.push_back(unsigned(pl.ops.size()));
+    unsigned long long before = 0;
+    for (POp op : tapes[j]->ops) {
+      op.chunk = unsigned(std::max<unsigned long long>(1, (op.tiles + target - 1) / target));
+      op.items = (op.tiles + op.chunk - 1) / op.chunk;
+      op.before = before;
+      before += op.items;
+      pl.ops.push_back(op);
+    }
+    pl.step_items.push_back(before);
+    n_slots = std::max(n_slots, tapes[j]->ops.size());
+  }
+  pl.slot_first.resize(n_slots * nprob);
+  for (size_t sl = 0; sl < n_slots; ++sl)
+    for (int j = 0; j < nprob; ++j) {
+      const size_t k = sl * nprob + j;
+      pl.slot_first[k] = pl.round_items;
+      if (sl < tapes[j]->ops.size()) {
+        const unsigned items = pl.ops[pl.op_begin[j] + sl].items;
+        pl.item_slot.insert(pl.item_slot.end(), items, unsigned(k));
+        pl.round_items += items;
+      }
+    }
+  size_t off = 256;   // ticket, n_active, error
+  pl.off_done = off;
+  off = align256(off + sizeof(unsigned long long) * nprob);
+  pl.off_active = off;
+  off = align256(off + sizeof(int*) * nprob);
+  pl.off_begin = off;
+  off = align256(off + sizeof(unsigned) * nprob);
+  pl.off_step = off;
+  off = align256(off + sizeof(unsigned long long) * nprob);
+  pl.off_ops = off;
+  off = align256(off + sizeof(POp) * pl.ops.size());
+  pl.off_first = off;
+  off = align256(off + sizeof(unsigned long long) * pl.slot_first.size());
+  pl.off_slot = off;
+  off = align256(off + sizeof(unsigned) * pl.item_slot.size());
+  pl.bytes = off;
+  return pl;
+}
+}  // namespace
+
+size_t persist_workspace_bytes(const PersistTape* const* tapes, int nprob, int blocks, int items_per_block) {
+  return plan_persist(tapes, nprob, blocks, items_per_block).bytes;
+}
+
+hipError_t persist_solve(const PersistTape* const* tapes, int nprob, int max_steps, int blocks, int items_per_block,
+                         unsigned spin_limit, void* ws, size_t ws_bytes, hipStream_t s, PersistResult* res) {
+  const PersistPlan pl = plan_persist(tapes, nprob, blocks, items_per_block);
+  if (!ws || ws_bytes < pl.bytes || (reinterpret_cast<uintptr_t>(ws) & 255)) return hipErrorInvalidValue;
+  if (pl.round_items == 0 || max_steps < 1 || blocks < 1) return hipErrorInvalidValue;
+  char* base = static_cast<char*>(ws);
+  std::vector<char> img(pl.bytes, 0);
+  int n_active = nprob;
+  std::memcpy(img.data() + 8, &n_active, sizeof(int));
+  std::vector<int*> act(nprob);
+  for (int j = 0; j < nprob; ++j) act[j] = tapes[j]->active;
+  std::memcpy(img.data() + pl.off_active, act.data(), sizeof(int*) * nprob);
+  std::memcpy(img.data() + pl.off_begin, pl.op_begin.data(), sizeof(unsigned) * nprob);
+  std::memcpy(img.data() + pl.off_step, pl.step_items.data(), sizeof(unsigned long long) * nprob);
+  std::memcpy(img.data() + pl.off_ops, pl.ops.data(), sizeof(POp) * pl.ops.size());
+  std::memcpy(img.data() + pl.off_first, pl.slot_first.data(), sizeof(unsigned long long) * pl.slot_first.size());
+  std::memcpy(img.data() + pl.off_slot, pl.item_slot.data(), sizeof(unsigned) * pl.item_slot.size());
+  hipError_t e = hipMemcpyAsync(base, img.data(), pl.bytes, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  PSched S;
+  S.op_begin = reinterpret_cast<const unsigned*>(base + pl.off_begin);
+  S.step_items = reinterpret_cast<const unsigned long long*>(base + pl.off_step);
+  S.active = reinterpret_cast<int* const*>(base + pl.off_active);
+  S.item_slot = reinterpret_cast<const unsigned*>(base + pl.off_slot);
+  S.slot_first = reinterpret_cast<const unsigned long long*>(base + pl.off_first);
+  S.round_items = pl.round_items;
+  S.total_items = pl.round_items * (unsigned long long)max_steps;
+  S.nprob = unsigned(nprob);
+  S.spin_limit = spin_limit;
+  S.ticket = reinterpret_cast<unsigned long long*>(base);
+  S.n_active = reinterpret_cast<int*>(base + 8);
+  S.error = reinterpret_cast<int*>(base + 12);
+  S.done = reinterpret_cast<unsigned long long*>(base + pl.off_done);
+  hipLaunchKernelGGL(k_persist, dim3(blocks), dim3(kBlock), 0, s, reinterpret_cast<const POp*>(base + pl.off_ops), S);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  char head[16];
+  e = hipMemcpyAsync(head, base, sizeof(head), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (res) {
+    std::memcpy(&res->tickets, head, 8);
+    std::memcpy(&res->n_active, head + 8, 4);
+    std::memcpy(&res->error, head + 12, 4);
+    res->round_items = pl.round_items;
+    res->blocks = blocks;
+  }
+  return hipSuccess;
+}
 
 }  // namespace ctf

@@ -28,7 +28,7 @@ EXPORTED = [
     "ctf_cnn_param_count", "ctf_cnn_workspace_bytes", "ctf_cnn_forward", "ctf_cnn_loss_grad",
     "ctf_cnn_adam", "ctf_cnn_attach", "ctf_cnn_enable", "ctf_cnn_sample",
     "ctf_solve_batch", "ctf_set_launch_shape", "ctf_get_launch_shape", "ctf_autotune",
-    "ctf_cnn_forward_noalloc",
+    "ctf_cnn_forward_noalloc", "ctf_solve_batch_persistent", "ctf_solve_batch_persistent_bytes",
 ]
 TIMER_CLASSES = ["pg64", "pg32", "upwind64", "upwind32", "corr0", "corrc", "restrict", "moments",
                  "emission", "norm", "moments_mfma", "cnn", "pgk64", "pgk32", "corr_scatter",
@@ -100,6 +100,9 @@ def load():
         "ctf_cnn_enable": (I, [P, I]),
         "ctf_cnn_sample": (I, [P, P, P, P, P, ctypes.POINTER(D)]),
         "ctf_solve_batch": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), D, I, I, ctypes.POINTER(SolveInfo)]),
+        "ctf_solve_batch_persistent": (I, [ctypes.POINTER(P), I, ctypes.POINTER(P), D, I, I, P, S,
+                                           ctypes.POINTER(SolveInfo)]),
+        "ctf_solve_batch_persistent_bytes": (S, [ctypes.POINTER(P), I, I]),
         "ctf_set_launch_shape": (I, [P, I, I, I]),
         "ctf_get_launch_shape": (I, [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
         "ctf_autotune": (I, [P, ctypes.c_char_p, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)]),
@@ -177,6 +180,26 @@ def solve_batch(problems, psis, rtol, max_steps, steps_per_graph=1):
     ps = (ctypes.c_void_p * n)(*[t.data_ptr() for t in psis])
     infos = (SolveInfo * n)()
     rc = _check(lib.ctf_solve_batch(hs, n, ps, rtol, max_steps, steps_per_graph, infos),
+                allow_not_converged=True)
+    return rc == CTF_OK, [{"cycles": i.cycles, "outer_steps": i.outer_steps, "rel_residual": i.rel_residual,
+                           "seconds": i.seconds} for i in infos]
+
+
+def solve_batch_persistent(problems, psis, rtol, max_steps, items_per_block=0):
+    """Solve several problems in one launch of the persistent kernel (ctf_solve_batch_persistent);
+    the schedule's workspace is a torch allocation on the problems' device."""
+    import torch
+    n = len(problems)
+    lib = load()
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    ps = (ctypes.c_void_p * n)(*[t.data_ptr() for t in psis])
+    nb = lib.ctf_solve_batch_persistent_bytes(hs, n, items_per_block)
+    if nb == 0:
+        raise CtfError(CTF_EINVAL, lib.ctf_last_error().decode())
+    ws = torch.empty(nb, dtype=torch.uint8, device=psis[0].device)
+    infos = (SolveInfo * n)()
+    rc = _check(lib.ctf_solve_batch_persistent(hs, n, ps, rtol, max_steps, items_per_block,
+                                               ctypes.c_void_p(ws.data_ptr()), nb, infos),
                 allow_not_converged=True)
     return rc == CTF_OK, [{"cycles": i.cycles, "outer_steps": i.outer_steps, "rel_residual": i.rel_residual,
                            "seconds": i.seconds} for i in infos]
