@@ -929,11 +929,13 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
                                w_outf = plane_rsrc(a.out_f ? a.out_f + base : nullptr, unsigned(ncell * 4)),
                                w_psif = plane_rsrc(a.psi_f ? a.psi_f + base : nullptr, unsigned(ncell * 4)),
                                w_acc = plane_rsrc(ACC ? a.acc64 + base : nullptr, unsigned(ncell * 8));
-  auto load_row = [&](int r) {
-    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n) * unsigned(sizeof(T));
+  // FAST: rows r and r - 4P need no clamping
+  auto load_row = [&](int r, auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    const unsigned ro = unsigned(FAST ? r : clampi(r, 0, n - 1)) * unsigned(n) * unsigned(sizeof(T));
     p0 = bload<T>(r_psi, b0, ro);
     p1 = bload<T>(r_psi, b1, ro);
-    const unsigned cr = unsigned(clampi(r - 4 * P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
+    const unsigned cr = unsigned(FAST ? r - 4 * P : clampi(r - 4 * P, y0, yend - 1)) * unsigned(n);   // rows of this strip only
     const unsigned co = cr * unsigned(sizeof(T));
     fe0 = bload<T>(r_e, bc, co);
     fe1 = bload<T>(r_e, bc, co + e1o);
@@ -943,178 +945,199 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     if (ACC) fy = bload<double>(r_y, b64, cr * 8u);
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
-  load_row(rbeg);
+  load_row(rbeg, std::false_type{});
   // ring slots of psi row r and Psi row r - P, advanced every step.  The k ring is as deep as the unrolled step count (KR = W) and numbered from this strip's first
   // row, so the k row formed at step t of an unrolled pass sits in slot t: every k slot is static.
   static_assert(KR == W, "k ring depth equals the unroll");
   int sp = ring_slot(rbeg, PR), sg = ring_slot(rbeg - P, GR);
-  for (int r0 = rbeg; r0 < rend; r0 += W) {
+  // One row step (t: its place in the unrolled pass).  FAST: a row of the strip's interior, where
+  // rows r + 1, r - 2P, r - 3P and r - 4P lie inside the domain and the strip (no clamping, no halo
+  // rows, the output row written): the bounds checks drop out of the compiled step.
+  auto step = [&](const int r, const int t, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+    T* const prow = s_psi[sp];
+    const bool zy = !FAST && ((r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0)));
+    const T v0 = (zy || zx0) ? T(0) : p0, v1 = (zy || zx1) ? T(0) : p1;
+    prow[lane] = v0;
+    prow[hidx] = lane < 2 * P ? v1 : v0;   // other lanes rewrite their own value
+    const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
+    const double y64 = fy;
+    load_row(r + 1, fast);   // past the last row this reloads a clamped row, unused
+    __syncthreads();
+    // A: Psi of row r - P
+    T* const gxr = &s_g[sg][0][P];
+    T* const gyr = &s_g[sg][1][P];
+    {
+      const T xd = xanti<P>(prow + lane, cd);
+      T xm = 0;
 #pragma unroll
-    for (int t = 0; t < W; ++t) {
-      const int r = r0 + t;
-      if (r >= rend) break;
-      T* const prow = s_psi[sp];
-      const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-      const T v0 = (zy || zx0) ? T(0) : p0, v1 = (zy || zx1) ? T(0) : p1;
-      prow[lane] = v0;
-      prow[hidx] = lane < 2 * P ? v1 : v0;   // other lanes rewrite their own value
-      const T e0 = fe0, e1 = fe1, e2 = fe2, rh = frh, sig = fs;
-      const double y64 = fy;
-      load_row(r + 1);   // past the last row this reloads a clamped row, unused
-      __syncthreads();
-      // A: Psi of row r - P
-      T* const gxr = &s_g[sg][0][P];
-      T* const gyr = &s_g[sg][1][P];
-      {
-        const T xd = xanti<P>(prow + lane, cd);
-        T xm = 0;
+      for (int u = 0; u < W; ++u) xm += cm[u] * prow[lane + u];
+      wXd[t] = xd;
+      wXm[t] = xm;
+      gxr[lane] = yrot(wXd, cm, t);
+      gyr[lane] = yanti(wXm, cd, t);
+      if constexpr (!MIXED) {
+        // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row; lq = lane on every lane
+        // whose k is read (P .. 63 - P)
+        const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
+        T qd = 0, qm = 0;
 #pragma unroll
-        for (int u = 0; u < W; ++u) xm += cm[u] * prow[lane + u];
-        wXd[t] = xd;
-        wXm[t] = xm;
-        gxr[lane] = yrot(wXd, cm, t);
-        gyr[lane] = yanti(wXm, cd, t);
-        if constexpr (!MIXED) {
-          // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row; lq = lane on every lane
-          // whose k is read (P .. 63 - P)
-          const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
-          T qd = 0, qm = 0;
-#pragma unroll
-          for (int u = 0; u < WQ; ++u) {
-            const T v = prow[lq + P - PQ + u];
-            qd += cdq[u] * v;
-            qm += cmq[u] * v;
-          }
-          push(wQd, qd);
-          push(wQm, qm);
+        for (int u = 0; u < WQ; ++u) {
+          const T v = prow[lq + P - PQ + u];
+          qd += cdq[u] * v;
+          qm += cmq[u] * v;
         }
+        push(wQd, qd);
+        push(wQm, qm);
       }
-      // the other-degree estimates read Psi of their own lane only: no wait for its neighbours
-      if constexpr (MIXED) __syncthreads();
-      // B: k of row r - 2P
-      {
-        if constexpr (MIXED) {
-          T mx = 0, my = 0;
-#pragma unroll
-          for (int u = 0; u < W; ++u) {
-            mx += cm[u] * gxr[lane - P + u];
-            my += cm[u] * gyr[lane - P + u];
-          }
-          wMx[t] = mx;
-          wMy[t] = my;
-        }
-        const int rk = r - 2 * P;
-        if (rk >= 0 && rk < n) {
-          const int gs = ring_back(sg, P, GR);
-          const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
-          T* const k0r = &s_k[t][0][P];
-          T* const k1r = &s_k[t][1][P];
-          if constexpr (!MIXED) {
-            // Psi of the other degree on row rk: y-pass over the window rows rk - Q .. rk + Q
-            T qx = 0, qy = 0;
-#pragma unroll
-            for (int v = 0; v < WQ; ++v) {
-              qx += cmq[v] * wQd[v];
-              qy += cdq[v] * wQm[v];
-            }
-            const T kk = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
-            k0r[lane] = kk;
-            k1r[lane] = kk;
-          } else if constexpr (RE == 3) {
-            const T rx = ar * mu * (yrot(wMx, cm, t) - px);
-            const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-            const T kk = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
-            k0r[lane] = kk;
-            k1r[lane] = kk;
-          } else {
-            const T rx = ar * mu * (yrot(wMx, cm, t) - px);
-            const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-            k0r[lane] = pg_k(kmx, amu, rx, px, cabs, csq, eps);
-            k1r[lane] = pg_k(kmy, anu, ry, py, cabs, csq, eps);
-          }
-          if (edge_strip) {
-            // columns outside the domain take k of the nearest interior column
-            __syncthreads();
-            const T ox = k0r[kcl], oy = k1r[kcl];
-            __syncthreads();
-            k0r[lane] = ox;
-            k1r[lane] = oy;
-          }
-        }
-      }
-      __syncthreads();
-      // C: x-passes of row s = r - 3P (k of the clamped row and columns)
-      {
-        const int srow = r - 3 * P;
-        const T* const spr = s_psi[ring_back(sp, 3 * P, PR)];
-        // k of row srow (formed P steps ago), or of the nearest interior row (formed at step row + 2P)
-        int ks = (t + W - P) % W;
-        if (srow < 0 || srow >= n) ks = int(unsigned(clampi(srow, 0, n - 1) + 2 * P - rbeg) % unsigned(W));
-        const T* const kxr = &s_k[ks][0][P];
-        const T* const kyr = &s_k[ks][1][P];
-        T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0;
+    }
+    // the other-degree estimates read Psi of their own lane only: no wait for its neighbours
+    if constexpr (MIXED) __syncthreads();
+    // B: k of row r - 2P
+    {
+      if constexpr (MIXED) {
+        T mx = 0, my = 0;
 #pragma unroll
         for (int u = 0; u < W; ++u) {
-          const T v = spr[lane + u];
-          const T kv = kxr[lane - P + u], qv = kyr[lane - P + u];
-          a1x += ck[u] * v;
-          a2x += ck[u] * (kv * v);
-          a3x += ck[u] * kv;
-          a1y += cm[u] * v;
-          a2y += cm[u] * (qv * v);
-          a3y += cm[u] * qv;
+          mx += cm[u] * gxr[lane - P + u];
+          my += cm[u] * gyr[lane - P + u];
         }
-        wA1x[t] = a1x;
-        wA2x[t] = a2x;
-        wA3x[t] = a3x;
-        wA1y[t] = a1y;
-        wA2y[t] = a2y;
-        wA3y[t] = a3y;
+        wMx[t] = mx;
+        wMy[t] = my;
       }
-      // D: output row r - 4P
-      const int o = r - 4 * P;
-      if (o >= y0 && writer) {
-        const int gs = ring_back(sg, 3 * P, GR), ks = (t + W - 2 * P) % W;
+      const int rk = r - 2 * P;
+      if (FAST || (rk >= 0 && rk < n)) {
+        const int gs = ring_back(sg, P, GR);
         const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
-        const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
-        const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
-        const T dx = ykdiff(wA1x, wA2x, wA3x, cm, t, kxc, psc);
-        const T dy = ykdiff(wA1y, wA2y, wA3y, ck, t, kyc, psc);
-        const unsigned orow = unsigned(o) * unsigned(n);
-        T q = e0;
-        if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
-        if (has_rhs) q = tfma(rsg, rh, q);
-        const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
-        if constexpr (BST) {
-          if (a.psi_f) bstore(float(psc), w_psif, bof, orow * 4u);
-          if (a.mode == 0) {
-            const T val = a.sign * rho;
-            if (a.out) bstore(val, w_out, bo, orow * unsigned(sizeof(T)));
-            if (a.out_f) bstore(float(val), w_outf, bof, orow * 4u);
-            if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
-          } else {
-            const T un = psc + qdiv(rho, diag + a.beta * sig);
-            bstore(un, w_out, bo, orow * unsigned(sizeof(T)));
-            if (ACC) bstore(y64 + (double(un) - double(float(y64))), w_acc, unsigned(col) * 8u, orow * 8u);
+        T* const k0r = &s_k[t][0][P];
+        T* const k1r = &s_k[t][1][P];
+        if constexpr (!MIXED) {
+          // Psi of the other degree on row rk: y-pass over the window rows rk - Q .. rk + Q
+          T qx = 0, qy = 0;
+#pragma unroll
+          for (int v = 0; v < WQ; ++v) {
+            qx += cmq[v] * wQd[v];
+            qy += cdq[v] * wQm[v];
           }
+          const T kk = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
+          k0r[lane] = kk;
+          k1r[lane] = kk;
+        } else if constexpr (RE == 3) {
+          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+          const T kk = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
+          k0r[lane] = kk;
+          k1r[lane] = kk;
         } else {
-          const size_t ro = base + size_t(orow);
-          if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
-          if (a.mode == 0) {
-            const T val = a.sign * rho;
-            if (a.out) at(a.out + ro, bo) = val;
-            if (a.out_f) at(a.out_f + ro, bof) = float(val);
-            if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
-          } else {
-            const T un = psc + qdiv(rho, diag + a.beta * sig);
-            at(a.out + ro, bo) = un;
-            if (ACC) at(a.acc64 + ro, unsigned(col) * 8u) = y64 + (double(un) - double(float(y64)));
-          }
+          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+          k0r[lane] = pg_k(kmx, amu, rx, px, cabs, csq, eps);
+          k1r[lane] = pg_k(kmy, anu, ry, py, cabs, csq, eps);
+        }
+        if (edge_strip) {
+          // columns outside the domain take k of the nearest interior column
+          __syncthreads();
+          const T ox = k0r[kcl], oy = k1r[kcl];
+          __syncthreads();
+          k0r[lane] = ox;
+          k1r[lane] = oy;
         }
       }
-      __syncthreads();   // the next step overwrites ring slots read above
-      sp = ring_next(sp, PR);
-      sg = ring_next(sg, GR);
+    }
+    __syncthreads();
+    // C: x-passes of row s = r - 3P (k of the clamped row and columns)
+    {
+      const int srow = r - 3 * P;
+      const T* const spr = s_psi[ring_back(sp, 3 * P, PR)];
+      // k of row srow (formed P steps ago), or of the nearest interior row (formed at step row + 2P)
+      int ks = (t + W - P) % W;
+      if (!FAST && (srow < 0 || srow >= n)) ks = int(unsigned(clampi(srow, 0, n - 1) + 2 * P - rbeg) % unsigned(W));
+      const T* const kxr = &s_k[ks][0][P];
+      const T* const kyr = &s_k[ks][1][P];
+      T a1x = 0, a2x = 0, a3x = 0, a1y = 0, a2y = 0, a3y = 0;
+#pragma unroll
+      for (int u = 0; u < W; ++u) {
+        const T v = spr[lane + u];
+        const T kv = kxr[lane - P + u], qv = kyr[lane - P + u];
+        a1x += ck[u] * v;
+        a2x += ck[u] * (kv * v);
+        a3x += ck[u] * kv;
+        a1y += cm[u] * v;
+        a2y += cm[u] * (qv * v);
+        a3y += cm[u] * qv;
+      }
+      wA1x[t] = a1x;
+      wA2x[t] = a2x;
+      wA3x[t] = a3x;
+      wA1y[t] = a1y;
+      wA2y[t] = a2y;
+      wA3y[t] = a3y;
+    }
+    // D: output row r - 4P
+    const int o = r - 4 * P;
+    if ((FAST || o >= y0) && writer) {
+      const int gs = ring_back(sg, 3 * P, GR), ks = (t + W - 2 * P) % W;
+      const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
+      const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
+      const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
+      const T dx = ykdiff(wA1x, wA2x, wA3x, cm, t, kxc, psc);
+      const T dy = ykdiff(wA1y, wA2y, wA3y, ck, t, kyc, psc);
+      const unsigned orow = unsigned(o) * unsigned(n);
+      T q = e0;
+      if (p1mom) q = emission_p1(q, e1, e2, mu, nu);
+      if (has_rhs) q = tfma(rsg, rh, q);
+      const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
+      if constexpr (BST) {
+        if (a.psi_f) bstore(float(psc), w_psif, bof, orow * 4u);
+        if (a.mode == 0) {
+          const T val = a.sign * rho;
+          if (a.out) bstore(val, w_out, bo, orow * unsigned(sizeof(T)));
+          if (a.out_f) bstore(float(val), w_outf, bof, orow * 4u);
+          if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
+        } else {
+          const T un = psc + qdiv(rho, diag + a.beta * sig);
+          bstore(un, w_out, bo, orow * unsigned(sizeof(T)));
+          if (ACC) bstore(y64 + (double(un) - double(float(y64))), w_acc, unsigned(col) * 8u, orow * 8u);
+        }
+      } else {
+        const size_t ro = base + size_t(orow);
+        if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
+        if (a.mode == 0) {
+          const T val = a.sign * rho;
+          if (a.out) at(a.out + ro, bo) = val;
+          if (a.out_f) at(a.out_f + ro, bof) = float(val);
+          if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
+        } else {
+          const T un = psc + qdiv(rho, diag + a.beta * sig);
+          at(a.out + ro, bo) = un;
+          if (ACC) at(a.acc64 + ro, unsigned(col) * 8u) = y64 + (double(un) - double(float(y64)));
+        }
+      }
+    }
+    __syncthreads();   // the next step overwrites ring slots read above
+    sp = ring_next(sp, PR);
+    sg = ring_next(sg, GR);
+  };
+  // the interior rows r in [flo, fhi) run the FAST step in whole unrolled passes aligned to rbeg
+  const int flo = y0 + 4 * P, fhi = min(n - 1, yend + 4 * P - 1);
+  const int f0 = rbeg + W * ((max(flo - rbeg, 0) + W - 1) / W);
+  int r0 = rbeg;
+  for (; r0 < rend && r0 < f0; r0 += W) {
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      if (r0 + t >= rend) break;
+      step(r0 + t, t, std::false_type{});
+    }
+  }
+  for (; r0 + W <= fhi; r0 += W) {
+#pragma unroll
+    for (int t = 0; t < W; ++t) step(r0 + t, t, std::true_type{});
+  }
+  for (; r0 < rend; r0 += W) {
+#pragma unroll
+    for (int t = 0; t < W; ++t) {
+      if (r0 + t >= rend) break;
+      step(r0 + t, t, std::false_type{});
     }
   }
   // norms are float64 only (a float32 launch with partial sums is refused by launch_pg)
