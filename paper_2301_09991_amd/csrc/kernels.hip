@@ -78,10 +78,6 @@ __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsign
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
-__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
-  typedef unsigned u2 __attribute__((ext_vector_type(2)));
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
-}
 
 // Anisotropic diffusivity of one direction component (eq. ano-k):
 //   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
@@ -810,11 +806,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
 //      column)
 //   D  output row r - 4P (y-passes over registers)
 // psi, Psi and k rows live in LDS rings deep enough for every later stage that reads them (the
-// centre values of row r - 4P included); the y-pass windows rotate with the unrolled step.
-__device__ __forceinline__ int ring_slot(int row, int depth) {
-  const int m = row % depth;
-  return m < 0 ? m + depth : m;
-}
+// centre values of psi and k at row r - 4P included; up to P = 2 those of Psi at row r - 4P are kept
+// in registers from stage B); the y-pass windows rotate with the unrolled step.
 // slot of the row `off` rows above the row in slot s (0 <= off < depth)
 __device__ __forceinline__ int ring_back(int s, int off, int depth) { return s >= off ? s - off : s - off + depth; }
 __device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == depth ? 0 : s + 1; }
@@ -825,7 +818,7 @@ __device__ __forceinline__ int ring_next(int s, int depth) { return s + 1 == dep
 // in stage A into shifted windows that reach back to row r - 2P - Q when stage B forms k of row
 // r - 2P).
 template <int P, int RE, typename T, bool ACC>
-__global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
+__global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) : 2) : 1) void k_pg_fused(PGArgs<T> a) {
   if (idle(a.L.dims.active)) return;
   static_assert(RE == 0 || RE == 3 || (RE == 1 && P >= 2) || (RE == 2 && P + 1 <= kMaxP),
                 "residual estimate degree");
@@ -835,8 +828,15 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   constexpr int WQ = 2 * PQ + 1;
   constexpr int KQ = MIXED ? 1 : 2 * P + PQ + 1;
   constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
-  constexpr int PR = 4 * P + 1;         // psi rows kept (r - 4P .. r)
-  constexpr int GR = 3 * P + 1;         // Psi rows kept (r - 4P .. r - P)
+  // Rings (slots numbered from the strip's first row).  Up to P = 2 (PS2) every slot is static: the
+  // psi ring (rows r - 4P .. r) is two unrolled passes deep (4P + 1 <= 2W) and the interior loop
+  // runs pairs of passes; the Psi ring holds rows r - 2P .. r - P in W slots (slot t: the row formed
+  // at step t), the Psi of row r - 4P that stage D needs being kept in registers from stage B.  At
+  // P >= 3 those registers and that unroll cost occupancy: the psi ring (4P + 1 rows) and the Psi
+  // ring (rows r - 4P .. r - P) take run-time slots.
+  constexpr bool PS2 = P <= 2;
+  constexpr int PR = PS2 ? 2 * W : 4 * P + 1;
+  constexpr int GR = PS2 ? W : 3 * P + 1;
   constexpr int KR = 2 * P + 1;         // k rows kept (r - 4P .. r - 2P)
   constexpr int OW = kStripW - 4 * P;   // columns written per strip
   // x and y components side by side, so that both are addressed from one base; Psi and k rows
@@ -880,6 +880,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     }
   }
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
+  // Psi of the lane's own column, row r - 2P, read again by stage D 2P steps later
+  T wDx[PS2 ? W : 1] = {}, wDy[PS2 ? W : 1] = {};
   T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
   // shifted windows (newest row last) of the other degree's x-passes
   T wQd[KQ] = {}, wQm[KQ] = {};
@@ -921,14 +923,10 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
                                r_rh = plane_rsrc(rhsp, pb), r_e = plane_rsrc(Eg, p1mom ? 3 * pb : pb),
                                r_y = plane_rsrc(yp, unsigned(ncell * 8));
   const unsigned e1o = p1mom ? pb : 0u, e2o = p1mom ? 2 * pb : 0u;
-  // output planes (an absent one is never written), through buffer stores in the float32 residual
-  // and sweep; the float64 kernel and the sweep with the float64 update keep plain stores (their
-  // scalar registers are short)
+  // the float32 residual and sweep write their one output plane through buffer stores; the float64
+  // kernel and the sweep with the float64 update keep plain stores (their scalar registers are short)
   constexpr bool BST = sizeof(T) == 4 && !ACC;
-  const __amdgpu_buffer_rsrc_t w_out = plane_rsrc(a.out ? a.out + base : nullptr, pb),
-                               w_outf = plane_rsrc(a.out_f ? a.out_f + base : nullptr, unsigned(ncell * 4)),
-                               w_psif = plane_rsrc(a.psi_f ? a.psi_f + base : nullptr, unsigned(ncell * 4)),
-                               w_acc = plane_rsrc(ACC ? a.acc64 + base : nullptr, unsigned(ncell * 8));
+  const __amdgpu_buffer_rsrc_t w_out = plane_rsrc(BST ? a.out + base : nullptr, pb);
   // FAST: rows r and r - 4P need no clamping
   auto load_row = [&](int r, auto fast) {
     constexpr bool FAST = decltype(fast)::value;
@@ -946,16 +944,15 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
   };
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg, std::false_type{});
-  // ring slots of psi row r and Psi row r - P, advanced every step.  The k ring is as deep as the unrolled step count (KR = W) and numbered from this strip's first
-  // row, so the k row formed at step t of an unrolled pass sits in slot t: every k slot is static.
-  static_assert(KR == W, "k ring depth equals the unroll");
-  int sp = ring_slot(rbeg, PR), sg = ring_slot(rbeg - P, GR);
-  // One row step (t: its place in the unrolled pass).  FAST: a row of the strip's interior, where
-  // rows r + 1, r - 2P, r - 3P and r - 4P lie inside the domain and the strip (no clamping, no halo
-  // rows, the output row written): the bounds checks drop out of the compiled step.
-  auto step = [&](const int r, const int t, auto fast) __attribute__((always_inline)) {
+  // The k ring is as deep as the unrolled pass (KR = W): the k row formed at step t sits in slot t.
+  static_assert(KR == W && (GR == W || !PS2), "k (and up to P = 2 Psi) ring depths equal the unroll");
+  // One row step (t: its place in the unrolled pass; ps, gsl: the psi slot of row r and the Psi slot
+  // of row r - P).  FAST: a row of the strip's interior, where rows r + 1, r - 2P, r - 3P and r - 4P
+  // lie inside the domain and the strip (no clamping, no halo rows, the output row written): the
+  // bounds checks drop out of the compiled step.
+  auto step = [&](const int r, const int t, const int ps, const int gsl, auto fast) __attribute__((always_inline)) {
     constexpr bool FAST = decltype(fast)::value;
-    T* const prow = s_psi[sp];
+    T* const prow = s_psi[ps];
     const bool zy = !FAST && ((r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0)));
     const T v0 = (zy || zx0) ? T(0) : p0, v1 = (zy || zx1) ? T(0) : p1;
     prow[lane] = v0;
@@ -965,8 +962,8 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     load_row(r + 1, fast);   // past the last row this reloads a clamped row, unused
     __syncthreads();
     // A: Psi of row r - P
-    T* const gxr = &s_g[sg][0][P];
-    T* const gyr = &s_g[sg][1][P];
+    T* const gxr = &s_g[gsl][0][P];
+    T* const gyr = &s_g[gsl][1][P];
     {
       const T xd = xanti<P>(prow + lane, cd);
       T xm = 0;
@@ -1007,8 +1004,12 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       }
       const int rk = r - 2 * P;
       if (FAST || (rk >= 0 && rk < n)) {
-        const int gs = ring_back(sg, P, GR);
+        const int gs = ring_back(gsl, P, GR);
         const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
+        if constexpr (PS2) {
+          wDx[t] = px;
+          wDy[t] = py;
+        }
         T* const k0r = &s_k[t][0][P];
         T* const k1r = &s_k[t][1][P];
         if constexpr (!MIXED) {
@@ -1048,7 +1049,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     // C: x-passes of row s = r - 3P (k of the clamped row and columns)
     {
       const int srow = r - 3 * P;
-      const T* const spr = s_psi[ring_back(sp, 3 * P, PR)];
+      const T* const spr = s_psi[ring_back(ps, 3 * P, PR)];
       // k of row srow (formed P steps ago), or of the nearest interior row (formed at step row + 2P)
       int ks = (t + W - P) % W;
       if (!FAST && (srow < 0 || srow >= n)) ks = int(unsigned(clampi(srow, 0, n - 1) + 2 * P - rbeg) % unsigned(W));
@@ -1076,9 +1077,21 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
     // D: output row r - 4P
     const int o = r - 4 * P;
     if ((FAST || o >= y0) && writer) {
-      const int gs = ring_back(sg, 3 * P, GR), ks = (t + W - 2 * P) % W;
-      const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
-      const T psc = s_psi[ring_back(sp, 4 * P, PR)][lane + P];
+      const int ks = (t + W - 2 * P) % W;
+      // up to P = 2 Psi of this row as read by stage B 2P steps ago, made opaque here so that no
+      // product stage B formed from it (the isotropic bound's nu Psi_y) is reused in this residual,
+      // which then contracts as in the two-pass kernel, bit for bit
+      T px, py;
+      if constexpr (PS2) {
+        px = wDx[ks % (PS2 ? W : 1)];
+        py = wDy[ks % (PS2 ? W : 1)];
+        asm volatile("" : "+v"(px), "+v"(py));
+      } else {
+        const int gs = ring_back(gsl, 3 * P, GR);
+        px = s_g[gs][0][P + lane];
+        py = s_g[gs][1][P + lane];
+      }
+      const T psc = s_psi[ring_back(ps, 4 * P, PR)][lane + P];
       const T kxc = s_k[ks][0][P + lane], kyc = s_k[ks][1][P + lane];
       const T dx = ykdiff(wA1x, wA2x, wA3x, cm, t, kxc, psc);
       const T dy = ykdiff(wA1y, wA2y, wA3y, ck, t, kyc, psc);
@@ -1088,17 +1101,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       if (has_rhs) q = tfma(rsg, rh, q);
       const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
       if constexpr (BST) {
-        if (a.psi_f) bstore(float(psc), w_psif, bof, orow * 4u);
-        if (a.mode == 0) {
-          const T val = a.sign * rho;
-          if (a.out) bstore(val, w_out, bo, orow * unsigned(sizeof(T)));
-          if (a.out_f) bstore(float(val), w_outf, bof, orow * 4u);
-          if constexpr (sizeof(T) == 8) acc += double(val) * double(val);
-        } else {
-          const T un = psc + qdiv(rho, diag + a.beta * sig);
-          bstore(un, w_out, bo, orow * unsigned(sizeof(T)));
-          if (ACC) bstore(y64 + (double(un) - double(float(y64))), w_acc, unsigned(col) * 8u, orow * 8u);
-        }
+        // float32: the one output `out` (a float32 launch with out_f or psi_f is refused)
+        if (a.mode == 0) bstore(a.sign * rho, w_out, bo, orow * 4u);
+        else bstore(psc + qdiv(rho, diag + a.beta * sig), w_out, bo, orow * 4u);
       } else {
         const size_t ro = base + size_t(orow);
         if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
@@ -1115,29 +1120,44 @@ __global__ __launch_bounds__(kStripW) void k_pg_fused(PGArgs<T> a) {
       }
     }
     __syncthreads();   // the next step overwrites ring slots read above
-    sp = ring_next(sp, PR);
-    sg = ring_next(sg, GR);
   };
-  // the interior rows r in [flo, fhi) run the FAST step in whole unrolled passes aligned to rbeg
+  // the interior rows r in [flo, fhi) run the FAST step in whole interior passes (FP rows: two
+  // unrolled passes up to P = 2, psi slot t of the pair; else one) aligned to rbeg; the head and
+  // tail passes take the psi slot at run time
+  constexpr int FP = PS2 ? 2 * W : W;
   const int flo = y0 + 4 * P, fhi = min(n - 1, yend + 4 * P - 1);
-  const int f0 = rbeg + W * ((max(flo - rbeg, 0) + W - 1) / W);
-  int r0 = rbeg;
-  for (; r0 < rend && r0 < f0; r0 += W) {
+  const int f0 = rbeg + FP * ((max(flo - rbeg, 0) + FP - 1) / FP);
+  int r0 = rbeg, half = 0, sp = 0, sg = 0;   // sp, sg: run-time slots (P >= 3)
+  for (; r0 < rend && r0 < f0; r0 += W, half ^= W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       if (r0 + t >= rend) break;
-      step(r0 + t, t, std::false_type{});
+      step(r0 + t, t, PS2 ? half + t : sp, PS2 ? t : sg, std::false_type{});
+      if constexpr (!PS2) {
+        sp = ring_next(sp, PR);
+        sg = ring_next(sg, GR);
+      }
     }
   }
-  for (; r0 + W <= fhi; r0 += W) {
+  for (; r0 + FP <= fhi; r0 += FP) {
 #pragma unroll
-    for (int t = 0; t < W; ++t) step(r0 + t, t, std::true_type{});
+    for (int t = 0; t < FP; ++t) {
+      step(r0 + t, t % W, PS2 ? t : sp, PS2 ? t % W : sg, std::true_type{});
+      if constexpr (!PS2) {
+        sp = ring_next(sp, PR);
+        sg = ring_next(sg, GR);
+      }
+    }
   }
-  for (; r0 < rend; r0 += W) {
+  for (; r0 < rend; r0 += W, half ^= W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       if (r0 + t >= rend) break;
-      step(r0 + t, t, std::false_type{});
+      step(r0 + t, t, PS2 ? half + t : sp, PS2 ? t : sg, std::false_type{});
+      if constexpr (!PS2) {
+        sp = ring_next(sp, PR);
+        sg = ring_next(sg, GR);
+      }
     }
   }
   // norms are float64 only (a float32 launch with partial sums is refused by launch_pg)
@@ -1874,7 +1894,8 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
-    // fused: the diffusivities of psi are formed on the fly
+    // fused: the diffusivities of psi are formed on the fly; in float32 into `out` alone
+    if (sizeof(T) == 4 && (!o.out || o.out_f || o.psi_f)) return hipErrorInvalidValue;
     if (pp.r_estimate && !pp.isotropic) return hipErrorInvalidValue;
     a.out = o.out;
     a.out_f = o.out_f;
