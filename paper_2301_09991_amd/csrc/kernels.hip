@@ -657,7 +657,9 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   constexpr int KQ = MIXED ? 1 : 2 * P + PQ + 1;
   constexpr int RW = kStripW + 2 * P;
   constexpr int OW = kStripW - 2 * P;   // columns written per strip
-  constexpr int D = P + 2;              // LDS ring of Psi rows: the newest and the P rows above it
+  // LDS ring of Psi rows (the newest and the P rows above it), as deep as the unrolled pass and
+  // numbered from the strip's first row: the Psi row formed at step t of a pass sits in slot t
+  constexpr int D = W;
   __shared__ T s_psi[RW];
   __shared__ T s_g[D][2][kStripW];   // Psi_x, Psi_y side by side
   const int n = a.L.dims.n;
@@ -702,97 +704,116 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   T p0, p1;
   const unsigned b0 = unsigned(cc0) * sizeof(T), b1 = unsigned(cc1) * sizeof(T);
   const unsigned bo = unsigned(gi) * sizeof(T), bof = unsigned(gi) * sizeof(float);
-  auto load_row = [&](int r) {
-    const unsigned ro = unsigned(clampi(r, 0, n - 1)) * unsigned(n);   // 32-bit in-plane offsets
+  // FAST: row r needs no clamping
+  auto load_row = [&](int r, auto fast) {
+    constexpr bool FAST = decltype(fast)::value;
+    const unsigned ro = unsigned(FAST ? r : clampi(r, 0, n - 1)) * unsigned(n);   // 32-bit in-plane offsets
     p0 = at(psi + ro, b0);
     p1 = at(psi + ro, b1);
   };
   const int rbeg = y0 - 2 * P, rend = yend + 2 * P;
-  load_row(rbeg);
-  int ring = 0;   // ring slot of the Psi row formed at this step
-  for (int r0 = rbeg; r0 < rend; r0 += W) {
+  load_row(rbeg, std::false_type{});
+  // One row step (t: its place in the unrolled pass).  FAST: a row of the strip's interior, where
+  // row r + 1 lies inside the domain and the output row is written.
+  auto step = [&](const int r, const int t, auto fast) __attribute__((always_inline)) {
+    constexpr bool FAST = decltype(fast)::value;
+    const bool zy = !FAST && ((r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0)));
+    s_psi[lane] = (zy || zx0) ? T(0) : p0;
+    if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : p1;
+    load_row(r + 1, fast);   // past the last row this reloads a clamped row, unused
+    __syncthreads();
+    const T xd = xanti<P>(s_psi + lane, cd);
+    T xm = 0;
+#pragma unroll
+    for (int u = 0; u < W; ++u) xm += cm[u] * s_psi[lane + u];
+    wXd[t] = xd;
+    wXm[t] = xm;
+    if constexpr (!MIXED) {
+      // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row buffer; lq = lane for
+      // every lane that writes
+      const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
+      T qd = 0, qm = 0;
+#pragma unroll
+      for (int u = 0; u < WQ; ++u) {
+        const T v = s_psi[lq + P - PQ + u];
+        qd += cdq[u] * v;
+        qm += cmq[u] * v;
+      }
+      push(wQd, qd);
+      push(wQm, qm);
+    }
+    // Psi on row r - P (meaningful once the window is full)
+    T* const gxr = s_g[t][0];
+    T* const gyr = s_g[t][1];
+    gxr[lane] = yrot(wXd, cm, t);
+    gyr[lane] = yanti(wXm, cd, t);
+    __syncthreads();
+    if constexpr (MIXED) {
+      T mx = 0, my = 0;
+      if (lane >= P && lane < kStripW - P) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          mx += cm[u] * gxr[lane - P + u];
+          my += cm[u] * gyr[lane - P + u];
+        }
+      }
+      wMx[t] = mx;
+      wMy[t] = my;
+    }
+    const int o = r - 2 * P;
+    if ((FAST || o >= y0) && writer) {
+      const int cs = (t + W - P) % W;   // ring slot of Psi row o
+      const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
+      T kx, ky;
+      if constexpr (!MIXED) {
+        // Psi of the other degree on row o: y-pass over the window rows o - Q .. o + Q
+        T qx = 0, qy = 0;
+#pragma unroll
+        for (int v = 0; v < WQ; ++v) {
+          qx += cmq[v] * wQd[v];
+          qy += cdq[v] * wQm[v];
+        }
+        kx = ky = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
+      } else {
+        const T rx = ar * mu * (yrot(wMx, cm, t) - px);
+        const T ry = ar * nu * (yrot(wMy, cm, t) - py);
+        if constexpr (RE == 3) {
+          kx = ky = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
+        } else {
+          kx = pg_k(kmx, amu, rx, px, cabs, csq, eps);
+          ky = pg_k(kmy, anu, ry, py, cabs, csq, eps);
+        }
+      }
+      const size_t ro = base + size_t(o) * n;
+      if (a.kx_out) {
+        at(a.kx_out + ro, bo) = kx;
+        at(a.ky_out + ro, bo) = ky;
+      }
+      if (a.kx_out_f) {
+        at(a.kx_out_f + ro, bof) = float(kx);
+        at(a.ky_out_f + ro, bof) = float(ky);
+      }
+    }
+  };
+  const int flo = y0 + 2 * P, fhi = min(n - 1, rend);
+  const int f0 = rbeg + W * ((max(flo - rbeg, 0) + W - 1) / W);
+  int r0 = rbeg;
+  for (; r0 < rend && r0 < f0; r0 += W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
-      const int r = r0 + t;
-      if (r >= rend) break;
-      const bool zy = (r < 0 && (a.bc_vac & 4) && nu > T(0)) || (r >= n && (a.bc_vac & 8) && nu < T(0));
-      s_psi[lane] = (zy || zx0) ? T(0) : p0;
-      if (lane < 2 * P) s_psi[kStripW + lane] = (zy || zx1) ? T(0) : p1;
-      load_row(r + 1);   // past the last row this reloads a clamped row, unused
-      __syncthreads();
-      const T xd = xanti<P>(s_psi + lane, cd);
-      T xm = 0;
+      if (r0 + t >= rend) break;
+      step(r0 + t, t, std::false_type{});
+    }
+  }
+  for (; r0 + W <= fhi; r0 += W) {
 #pragma unroll
-      for (int u = 0; u < W; ++u) xm += cm[u] * s_psi[lane + u];
-      wXd[t] = xd;
-      wXm[t] = xm;
-      if constexpr (!MIXED) {
-        // taps lq - 1 .. lq + 2P + 1 (degree P + 1) stay inside the row buffer; lq = lane for
-        // every lane that writes
-        const int lq = RE == 2 ? clampi(lane, 1, kStripW - 2) : lane;
-        T qd = 0, qm = 0;
+    for (int t = 0; t < W; ++t) step(r0 + t, t, std::true_type{});
+  }
+  for (; r0 < rend; r0 += W) {
 #pragma unroll
-        for (int u = 0; u < WQ; ++u) {
-          const T v = s_psi[lq + P - PQ + u];
-          qd += cdq[u] * v;
-          qm += cmq[u] * v;
-        }
-        push(wQd, qd);
-        push(wQm, qm);
-      }
-      // Psi on row r - P (meaningful once the window is full)
-      T* const gxr = s_g[ring][0];
-      T* const gyr = s_g[ring][1];
-      gxr[lane] = yrot(wXd, cm, t);
-      gyr[lane] = yanti(wXm, cd, t);
-      __syncthreads();
-      if constexpr (MIXED) {
-        T mx = 0, my = 0;
-        if (lane >= P && lane < kStripW - P) {
-#pragma unroll
-          for (int u = 0; u < W; ++u) {
-            mx += cm[u] * gxr[lane - P + u];
-            my += cm[u] * gyr[lane - P + u];
-          }
-        }
-        wMx[t] = mx;
-        wMy[t] = my;
-      }
-      const int o = r - 2 * P;
-      if (o >= y0 && writer) {
-        const int cs = ring >= P ? ring - P : ring + D - P;   // ring slot of Psi row o
-        const T px = s_g[cs][0][lane], py = s_g[cs][1][lane];
-        T kx, ky;
-        if constexpr (!MIXED) {
-          // Psi of the other degree on row o: y-pass over the window rows o - Q .. o + Q
-          T qx = 0, qy = 0;
-#pragma unroll
-          for (int v = 0; v < WQ; ++v) {
-            qx += cmq[v] * wQd[v];
-            qy += cdq[v] * wQm[v];
-          }
-          kx = ky = pg_k_iso(mu, nu, pg_r_other_degree<RE>(mu, nu, px, py, qx, qy), px, py, kmi, cabs, csq, eps);
-        } else {
-          const T rx = ar * mu * (yrot(wMx, cm, t) - px);
-          const T ry = ar * nu * (yrot(wMy, cm, t) - py);
-          if constexpr (RE == 3) {
-            kx = ky = pg_k_iso(mu, nu, pg_r_mixed(rx, ry), px, py, kmi, cabs, csq, eps);
-          } else {
-            kx = pg_k(kmx, amu, rx, px, cabs, csq, eps);
-            ky = pg_k(kmy, anu, ry, py, cabs, csq, eps);
-          }
-        }
-        const size_t ro = base + size_t(o) * n;
-        if (a.kx_out) {
-          at(a.kx_out + ro, bo) = kx;
-          at(a.ky_out + ro, bo) = ky;
-        }
-        if (a.kx_out_f) {
-          at(a.kx_out_f + ro, bof) = float(kx);
-          at(a.ky_out_f + ro, bof) = float(ky);
-        }
-      }
-      ring = ring + 1 == D ? 0 : ring + 1;
+    for (int t = 0; t < W; ++t) {
+      if (r0 + t >= rend) break;
+      step(r0 + t, t, std::false_type{});
     }
   }
 }
@@ -1891,11 +1912,12 @@ hipError_t launch_pg(int p, const LevelData<T>& L, const Stencils<T>& st, const 
                      const PGLaunch<T>& o, hipStream_t s) {
   if (g_tape) return tape_refuse();
   if (sizeof(T) == 4 && o.partial) return hipErrorInvalidValue;   // the float32 kernels form no norms
+  // the float32 kernels write their one output plane `out`
+  if (sizeof(T) == 4 && (!o.out || o.out_f || o.psi_f)) return hipErrorInvalidValue;
   PGArgs<T> a = pg_args(L, st, pp, o);
   const int n = L.dims.n;
   if (!o.kx_in && !o.kx_out && !o.kx_out_f) {
-    // fused: the diffusivities of psi are formed on the fly; in float32 into `out` alone
-    if (sizeof(T) == 4 && (!o.out || o.out_f || o.psi_f)) return hipErrorInvalidValue;
+    // fused: the diffusivities of psi are formed on the fly
     if (pp.r_estimate && !pp.isotropic) return hipErrorInvalidValue;
     a.out = o.out;
     a.out_f = o.out_f;

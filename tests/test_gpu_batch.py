@@ -107,6 +107,24 @@ def test_results_do_not_depend_on_launch_shape(disc, precision):
         assert np.array_equal(o, outs[0][0]) and np.array_equal(x, outs[0][1])
 
 
+@pytest.mark.parametrize("precision", [0, 1])
+def test_wide_sweep_blocks_give_the_same_bits(precision):
+    """Sweep blocks of 1024 and of 256 threads on a ragged grid wider than 256 nodes (288): the
+    same cycle iterates, bit for bit."""
+    import torch
+    ctf = _ctf()
+    op, gp = make_pair(workload(N=288, na=1, G=1), "upwind", "vac", precision=precision)
+    psi0 = torch.as_tensor(random_field(op.shape(), seed=9, lo=0.0, hi=1.0), device="cuda")
+    outs = []
+    for block in (256, 1024):
+        gp.set_launch_shape(128, block, 1)
+        x = psi0.clone()
+        for _ in range(2):
+            gp.mg_cycle(x)
+        outs.append(x.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_autotune_picks_and_caches_a_shape():
     ctf = _ctf()
     w = Workload("tune", 96, 1.0, 2, 4, 1, 8, "iso", "box_quarter", seed=3)
