@@ -866,9 +866,10 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   P->pp.bc_vac = P->bc_vac;
   P->pp.isotropic = cfg->pg_isotropic;
   P->pp.r_estimate = cfg->discretisation == CTF_UPWIND ? 0 : cfg->pg_r_estimate;
-  // default launch shape: the single-pass PG form up to p = 2, the stored-diffusivity form above
-  // (fewer registers per wave; measured faster at p = 3 in both precisions)
-  P->pg_fused = cfg->p >= 3 ? 0 : 1;
+  // default launch shape: the single-pass PG form up to p = 3 (at p = 3 on the 512^2 x 2048 x 4
+  // workload with 256-row strips: float32 sweep 18.6 ms vs 11.7 + 8.1 ms stored-diffusivity, float64
+  // residual 39.0 vs 22.4 + 17.4 ms), the stored-diffusivity form at p = 4 (not measured)
+  P->pg_fused = cfg->p >= 4 ? 0 : 1;
   // strips of 256 rows instead of 128 once the PG launch still has at least eight rounds of the
   // chip's 4096 wavefront slots: fewer halo rows per output row (7p per strip), measured 2% faster
   // on the 1024^2 x 512 workload; smaller problems keep 128 rows to fill the chip
