@@ -205,19 +205,23 @@ __global__ __launch_bounds__(kB) void k_conv_bwd_data(const float* __restrict__ 
 }
 
 // ---- backward weights: one block per (co, ci): 9 taps; the bias gradient rides on ci == 0 ------
+// Each thread sums its pixels p, p + kB, ... in that order in float64.  The pixel loop runs four
+// pixels per pass with every load issued first (eight: fewer waves, slower); taps outside the image and zero gradients (the
+// ReLU's) contribute an exact zero product instead of being skipped, which leaves every partial
+// sum unchanged, so the result is that of summing the nonzero terms alone.
 template <int CI, int CO>
 __global__ __launch_bounds__(kB) void k_conv_bwd_weight(const float* __restrict__ dz, const float* __restrict__ in,
                                                         float* __restrict__ gW, float* __restrict__ gb,
                                                         int B, int H, int Wd) {
   const int co = blockIdx.x / CI, ci = blockIdx.x - co * CI;
-  const int hw = H * Wd;
+  const int hw = H * Wd, total = B * hw;
   double acc[10];
 #pragma unroll
   for (int t = 0; t < 10; ++t) acc[t] = 0.0;
-  for (int p = threadIdx.x; p < B * hw; p += kB) {
+  // the gradient and the nine taps of pixel p (taps outside the image read as 0)
+  auto load = [&](int p, float& g, float (&sv)[9]) {
     const int b = p / hw, r = p - b * hw, y = r / Wd, x = r - y * Wd;
-    const float g = dz[(size_t(b) * CO + co) * hw + r];
-    if (g == 0.f) continue;
+    g = dz[(size_t(b) * CO + co) * hw + r];
     const float* src = in + (size_t(b) * CI + ci) * hw;
 #pragma unroll
     for (int v = 0; v < 3; ++v) {
@@ -225,10 +229,30 @@ __global__ __launch_bounds__(kB) void k_conv_bwd_weight(const float* __restrict_
 #pragma unroll
       for (int u = 0; u < 3; ++u) {
         const int xx = x + u - 1;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < Wd) acc[v * 3 + u] += double(g) * double(src[yy * Wd + xx]);
+        const bool ok = yy >= 0 && yy < H && xx >= 0 && xx < Wd;
+        sv[v * 3 + u] = src[ok ? yy * Wd + xx : r];
+        if (!ok) sv[v * 3 + u] = 0.f;
       }
     }
+  };
+  auto add = [&](float g, const float (&sv)[9]) {
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] += double(g) * double(sv[t]);
     acc[9] += double(g);
+  };
+  constexpr int U = 4;
+  int p = threadIdx.x;
+  for (; p + (U - 1) * kB < total; p += U * kB) {
+    float g[U], sv[U][9];
+#pragma unroll
+    for (int k = 0; k < U; ++k) load(p + k * kB, g[k], sv[k]);
+#pragma unroll
+    for (int k = 0; k < U; ++k) add(g[k], sv[k]);
+  }
+  for (; p < total; p += kB) {
+    float g, sv[9];
+    load(p, g, sv);
+    add(g, sv);
   }
   __shared__ double red[10][kB];
 #pragma unroll

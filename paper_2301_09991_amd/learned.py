@@ -81,17 +81,20 @@ def train(features, targets, epochs=60, batch=16, lr=1e-3, seed=0, bf16=True, lo
     rng = np.random.Generator(np.random.PCG64(seed + 1))
     history, step = [], 0
     for ep in range(epochs):
-        perm = rng.permutation(S)
-        losses = []
+        # the epoch's order goes to the device once and its losses are summed there: one host
+        # synchronisation per epoch
+        perm = torch.as_tensor(rng.permutation(S), device=theta.device)
+        loss_sum = torch.zeros(1, dtype=torch.float64, device=theta.device)
+        nb = 0
         for b0 in range(0, S - batch + 1, batch):
-            idx = torch.as_tensor(perm[b0:b0 + batch], device="cuda")
+            idx = perm[b0:b0 + batch]
             x = features.index_select(0, idx).contiguous()
             t = targets.index_select(0, idx).contiguous()
-            loss = net.loss_grad(theta, x, t, grad, bf16=bf16)
+            loss_sum += net.loss_grad(theta, x, t, grad, bf16=bf16)
+            nb += 1
             step += 1
             net.adam(theta, m, v, grad, step, lr)
-            losses.append(loss.item())
-        history.append(float(np.mean(losses)) if losses else float("nan"))
+        history.append(float(loss_sum.item()) / nb if nb else float("nan"))
         if log:
             log(f"epoch {ep}: loss {history[-1]:.4e}")
     return theta, history
