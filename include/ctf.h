@@ -240,8 +240,9 @@ int ctf_solve(ctf_problem* prob, double* psi, double rtol, int max_cycles, ctf_s
  * once, so converged problems drop out without host involvement; the host reads the flags only
  * between replays.  psis[i] is problem i's angular flux (in place, warm start); infos (nprob
  * entries, optional) receive per-problem cycles, outer steps, final residual and the call's wall
- * time.  The problems must be distinct; their own streams must be idle.  Returns CTF_OK when all
- * converged, CTF_NOT_CONVERGED otherwise. */
+ * time.  The problems must be distinct; their own streams must be idle.  Every problem's flag is set
+ * again before the call returns, so the problems stay usable.  Returns CTF_OK when all converged,
+ * CTF_NOT_CONVERGED otherwise. */
 int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, double rtol,
                     int max_steps, int steps_per_graph, ctf_solve_info* infos);
 
@@ -260,7 +261,8 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
  * release and acquire of memory).  workspace: device memory of ctf_solve_batch_persistent_bytes()
  * bytes, 256-byte aligned, owned by the caller (the schedule and the counters; overwritten).  Runs
  * on the first problem's stream and returns when the launch has finished; the problems' own
- * streams must be idle.  Returns CTF_OK when all converged, CTF_NOT_CONVERGED otherwise. */
+ * streams must be idle.  Every problem's flag is set again before the call returns.  Returns CTF_OK
+ * when all converged, CTF_NOT_CONVERGED otherwise. */
 int ctf_solve_batch_persistent(ctf_problem* const* probs, int nprob, double* const* psis, double rtol,
                                int max_steps, int items_per_block, void* workspace, size_t ws_bytes,
                                ctf_solve_info* infos);

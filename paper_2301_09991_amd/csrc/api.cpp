@@ -1232,6 +1232,9 @@ int ctf_solve_batch(ctf_problem* const* probs, int nprob, double* const* psis, d
   auto cleanup = [&]() {
     for (int i = 0; i < nprob; ++i) {
       probs[i]->stream = saved[i] ? saved[i] : probs[i]->stream;
+      // every problem leaves active again: the flag gates all of its kernels, also outside a batch
+      (void)launch_set_int(probs[i]->active, 1, probs[i]->stream);
+      (void)hipStreamSynchronize(probs[i]->stream);
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1425,6 +1428,9 @@ int ctf_solve_batch_persistent(ctf_problem* const* probs, int nprob, double* con
                            probs[0]->stream));
     CTF_HIP(hipMemcpyAsync(&act[i], probs[i]->active, sizeof(int), hipMemcpyDeviceToHost, probs[0]->stream));
   }
+  CTF_HIP(hipStreamSynchronize(probs[0]->stream));
+  // every problem leaves active again: the flag gates all of its kernels, also outside a batch
+  for (int i = 0; i < nprob; ++i) CTF_HIP(launch_set_int(probs[i]->active, 1, probs[0]->stream));
   CTF_HIP(hipStreamSynchronize(probs[0]->stream));
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   bool any = false;

@@ -49,23 +49,29 @@ def generate_samples(workloads, make_inputs, cnn_level=0, cycles=SAMPLE_CYCLES, 
     import torch
     feats, tgts = [], []
     kmax = max(cycles)
-    for item in workloads:
-        w, lvl = item if isinstance(item, tuple) else (item, cnn_level)
-        prob = make_problem(w, make_inputs(w), lvl, disc=disc)
-        star = prob.zeros()
-        prob.solve(star, star_rtol, max_cycles)
-        nc = prob.cnn_grid()
-        psi = prob.zeros()
-        for k in range(1, kmax + 1):
-            if k in cycles:
-                f = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
-                t = torch.empty((1, nc, nc), dtype=torch.float32, device="cuda")
-                prob.cnn_sample(psi, star, f, t)
-                feats.append(f)
-                tgts.append(t)
-            else:
-                prob.mg_cycle(psi)
-        del prob
+    # the reference solutions psi* of a group of problems in one batched solve (the iterates of
+    # individual solves, bit for bit), then the sampling cycles problem by problem
+    group = 64
+    for g0 in range(0, len(workloads), group):
+        probs, stars = [], []
+        for item in workloads[g0:g0 + group]:
+            w, lvl = item if isinstance(item, tuple) else (item, cnn_level)
+            probs.append(make_problem(w, make_inputs(w), lvl, disc=disc))
+            stars.append(probs[-1].zeros())
+        ctf.solve_batch(probs, stars, star_rtol, max_cycles, 4)
+        for prob, star in zip(probs, stars):
+            nc = prob.cnn_grid()
+            psi = prob.zeros()
+            for k in range(1, kmax + 1):
+                if k in cycles:
+                    f = torch.empty((3, nc, nc), dtype=torch.float32, device="cuda")
+                    t = torch.empty((1, nc, nc), dtype=torch.float32, device="cuda")
+                    prob.cnn_sample(psi, star, f, t)
+                    feats.append(f)
+                    tgts.append(t)
+                else:
+                    prob.mg_cycle(psi)
+        del probs, stars
     return torch.stack(feats), torch.stack(tgts)
 
 

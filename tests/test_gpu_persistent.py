@@ -140,3 +140,27 @@ def test_persistent_refusals():
         rc = lib.ctf_solve_batch_persistent(hs, 1, ps, 1e-6, 10, 0, ctypes.c_void_p(ws.data_ptr()), nb, infos)
         assert rc == expect
         assert float(x.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_problems_stay_usable_after_a_batch(persistent):
+    """A batch leaves every problem active: a cycle afterwards gives the bits of the same cycle on a
+    fresh problem (regression: converged problems kept their flag cleared, so every later kernel of
+    theirs returned at once)."""
+    ctf = _ctf()
+    ws = _uneven("pu", [16, 24], 3700)
+    probs = [_problem(w, 1) for w in ws]
+    psis = [p.zeros() for p in probs]
+    if persistent:
+        ok, _ = ctf.solve_batch_persistent(probs, psis, 1e-6, 200)
+    else:
+        ok, _ = ctf.solve_batch(probs, psis, 1e-6, 200, 2)
+    assert ok
+    for w, prob, psi in zip(ws, probs, psis):
+        x = psi.clone()
+        prob.mg_cycle(x)
+        fresh = _problem(w, 1)
+        y = psi.clone()
+        fresh.mg_cycle(y)
+        assert not np.array_equal(x.cpu().numpy(), psi.cpu().numpy())
+        assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
