@@ -78,6 +78,10 @@ __device__ __forceinline__ double bload<double>(__amdgpu_buffer_rsrc_t r, unsign
 __device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, voff, soff, 0);
 }
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  typedef unsigned u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, voff, soff, 0);
+}
 
 // Anisotropic diffusivity of one direction component (eq. ano-k):
 //   k = min(h|mu|, akabs |R| h / (eps + |Psi|), aksq R^2 h / (eps + |mu| Psi^2))
@@ -944,10 +948,12 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
                                r_rh = plane_rsrc(rhsp, pb), r_e = plane_rsrc(Eg, p1mom ? 3 * pb : pb),
                                r_y = plane_rsrc(yp, unsigned(ncell * 8));
   const unsigned e1o = p1mom ? pb : 0u, e2o = p1mom ? 2 * pb : 0u;
-  // the float32 residual and sweep write their one output plane through buffer stores; the float64
-  // kernel and the sweep with the float64 update keep plain stores (their scalar registers are short)
-  constexpr bool BST = sizeof(T) == 4 && !ACC;
-  const __amdgpu_buffer_rsrc_t w_out = plane_rsrc(BST ? a.out + base : nullptr, pb);
+  // the float32 residual and sweep write their one output plane (and the sweep with the float64
+  // update its float64 plane) through buffer stores; the float64 kernel keeps plain stores (its
+  // scalar registers are short)
+  constexpr bool BST = sizeof(T) == 4;
+  const __amdgpu_buffer_rsrc_t w_out = plane_rsrc(BST ? a.out + base : nullptr, pb),
+                               w_acc = plane_rsrc(BST && ACC ? a.acc64 + base : nullptr, unsigned(ncell * 8));
   // FAST: rows r and r - 4P need no clamping
   auto load_row = [&](int r, auto fast) {
     constexpr bool FAST = decltype(fast)::value;
@@ -1123,8 +1129,13 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
       const T rho = q - mu * px - nu * py - dx - dy - sig * psc;
       if constexpr (BST) {
         // float32: the one output `out` (a float32 launch with out_f or psi_f is refused)
-        if (a.mode == 0) bstore(a.sign * rho, w_out, bo, orow * 4u);
-        else bstore(psc + qdiv(rho, diag + a.beta * sig), w_out, bo, orow * 4u);
+        if (a.mode == 0) {
+          bstore(a.sign * rho, w_out, bo, orow * 4u);
+        } else {
+          const T un = psc + qdiv(rho, diag + a.beta * sig);
+          bstore(un, w_out, bo, orow * 4u);
+          if constexpr (ACC) bstore(y64 + (double(un) - double(float(y64))), w_acc, unsigned(col) * 8u, orow * 8u);
+        }
       } else {
         const size_t ro = base + size_t(orow);
         if (a.psi_f) at(a.psi_f + ro, bof) = float(psc);
