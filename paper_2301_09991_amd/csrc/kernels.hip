@@ -853,15 +853,17 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
   constexpr int WQ = 2 * PQ + 1;
   constexpr int KQ = MIXED ? 1 : 2 * P + PQ + 1;
   constexpr int RW = kStripW + 2 * P;   // psi row with a P-column halo
-  // Rings (slots numbered from the strip's first row).  Up to P = 2 (PS2) every slot is static: the
-  // psi ring (rows r - 4P .. r) is two unrolled passes deep (4P + 1 <= 2W) and the interior loop
-  // runs pairs of passes; the Psi ring holds rows r - 2P .. r - P in W slots (slot t: the row formed
-  // at step t), the Psi of row r - 4P that stage D needs being kept in registers from stage B.  At
-  // P >= 3 those registers and that unroll cost occupancy: the psi ring (4P + 1 rows) and the Psi
-  // ring (rows r - 4P .. r - P) take run-time slots.
+  // Rings (slots numbered from the strip's first row).  Up to P = 2 (PS2) the psi ring (rows
+  // r - 4P .. r) is two unrolled passes deep (4P + 1 <= 2W) and the interior loop runs pairs of
+  // passes, so its slots are static; at P >= 3 that unroll costs occupancy and the ring (4P + 1
+  // rows) takes run-time slots.  With GS (up to P = 2, and at P = 3 in float32) the Psi ring holds
+  // rows r - 2P .. r - P in W static slots (slot t: the row formed at step t), the Psi of row
+  // r - 4P that stage D needs being kept in registers from stage B; otherwise (float64 at P = 3,
+  // P = 4: those registers would cost occupancy) it holds rows r - 4P .. r - P in run-time slots.
   constexpr bool PS2 = P <= 2;
+  constexpr bool GS = P <= 2 || (P == 3 && sizeof(T) == 4);
   constexpr int PR = PS2 ? 2 * W : 4 * P + 1;
-  constexpr int GR = PS2 ? W : 3 * P + 1;
+  constexpr int GR = GS ? W : 3 * P + 1;
   constexpr int KR = 2 * P + 1;         // k rows kept (r - 4P .. r - 2P)
   constexpr int OW = kStripW - 4 * P;   // columns written per strip
   // x and y components side by side, so that both are addressed from one base; Psi and k rows
@@ -906,7 +908,7 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
   }
   T wXd[W] = {}, wXm[W] = {}, wMx[W] = {}, wMy[W] = {};
   // Psi of the lane's own column, row r - 2P, read again by stage D 2P steps later
-  T wDx[PS2 ? W : 1] = {}, wDy[PS2 ? W : 1] = {};
+  T wDx[GS ? W : 1] = {}, wDy[GS ? W : 1] = {};
   T wA1x[W] = {}, wA2x[W] = {}, wA3x[W] = {}, wA1y[W] = {}, wA2y[W] = {}, wA3y[W] = {};
   // shifted windows (newest row last) of the other degree's x-passes
   T wQd[KQ] = {}, wQm[KQ] = {};
@@ -972,7 +974,7 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
   const int rbeg = y0 - 3 * P, rend = yend + 4 * P;
   load_row(rbeg, std::false_type{});
   // The k ring is as deep as the unrolled pass (KR = W): the k row formed at step t sits in slot t.
-  static_assert(KR == W && (GR == W || !PS2), "k (and up to P = 2 Psi) ring depths equal the unroll");
+  static_assert(KR == W && (GR == W || !GS), "k (and with GS Psi) ring depths equal the unroll");
   // One row step (t: its place in the unrolled pass; ps, gsl: the psi slot of row r and the Psi slot
   // of row r - P).  FAST: a row of the strip's interior, where rows r + 1, r - 2P, r - 3P and r - 4P
   // lie inside the domain and the strip (no clamping, no halo rows, the output row written): the
@@ -1033,7 +1035,7 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
       if (FAST || (rk >= 0 && rk < n)) {
         const int gs = ring_back(gsl, P, GR);
         const T px = s_g[gs][0][P + lane], py = s_g[gs][1][P + lane];
-        if constexpr (PS2) {
+        if constexpr (GS) {
           wDx[t] = px;
           wDy[t] = py;
         }
@@ -1105,13 +1107,13 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
     const int o = r - 4 * P;
     if ((FAST || o >= y0) && writer) {
       const int ks = (t + W - 2 * P) % W;
-      // up to P = 2 Psi of this row as read by stage B 2P steps ago, made opaque here so that no
+      // with GS, Psi of this row as read by stage B 2P steps ago, made opaque here so that no
       // product stage B formed from it (the isotropic bound's nu Psi_y) is reused in this residual,
       // which then contracts as in the two-pass kernel, bit for bit
       T px, py;
-      if constexpr (PS2) {
-        px = wDx[ks % (PS2 ? W : 1)];
-        py = wDy[ks % (PS2 ? W : 1)];
+      if constexpr (GS) {
+        px = wDx[ks % (GS ? W : 1)];
+        py = wDy[ks % (GS ? W : 1)];
         asm volatile("" : "+v"(px), "+v"(py));
       } else {
         const int gs = ring_back(gsl, 3 * P, GR);
@@ -1159,37 +1161,31 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
   constexpr int FP = PS2 ? 2 * W : W;
   const int flo = y0 + 4 * P, fhi = min(n - 1, yend + 4 * P - 1);
   const int f0 = rbeg + FP * ((max(flo - rbeg, 0) + FP - 1) / FP);
-  int r0 = rbeg, half = 0, sp = 0, sg = 0;   // sp, sg: run-time slots (P >= 3)
+  int r0 = rbeg, half = 0, sp = 0, sg = 0;   // sp, sg: run-time slots (without PS2, GS)
   for (; r0 < rend && r0 < f0; r0 += W, half ^= W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       if (r0 + t >= rend) break;
-      step(r0 + t, t, PS2 ? half + t : sp, PS2 ? t : sg, std::false_type{});
-      if constexpr (!PS2) {
-        sp = ring_next(sp, PR);
-        sg = ring_next(sg, GR);
-      }
+      step(r0 + t, t, PS2 ? half + t : sp, GS ? t : sg, std::false_type{});
+      if constexpr (!PS2) sp = ring_next(sp, PR);
+      if constexpr (!GS) sg = ring_next(sg, GR);
     }
   }
   for (; r0 + FP <= fhi; r0 += FP) {
 #pragma unroll
     for (int t = 0; t < FP; ++t) {
-      step(r0 + t, t % W, PS2 ? t : sp, PS2 ? t % W : sg, std::true_type{});
-      if constexpr (!PS2) {
-        sp = ring_next(sp, PR);
-        sg = ring_next(sg, GR);
-      }
+      step(r0 + t, t % W, PS2 ? t : sp, GS ? t % W : sg, std::true_type{});
+      if constexpr (!PS2) sp = ring_next(sp, PR);
+      if constexpr (!GS) sg = ring_next(sg, GR);
     }
   }
   for (; r0 < rend; r0 += W, half ^= W) {
 #pragma unroll
     for (int t = 0; t < W; ++t) {
       if (r0 + t >= rend) break;
-      step(r0 + t, t, PS2 ? half + t : sp, PS2 ? t : sg, std::false_type{});
-      if constexpr (!PS2) {
-        sp = ring_next(sp, PR);
-        sg = ring_next(sg, GR);
-      }
+      step(r0 + t, t, PS2 ? half + t : sp, GS ? t : sg, std::false_type{});
+      if constexpr (!PS2) sp = ring_next(sp, PR);
+      if constexpr (!GS) sg = ring_next(sg, GR);
     }
   }
   // norms are float64 only (a float32 launch with partial sums is refused by launch_pg)
