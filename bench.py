@@ -529,9 +529,9 @@ def main():
                     help="other workloads whose step throughput is reported beside the headline ('' for none)")
     ap.add_argument("--also-steps", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the time-to-tolerance and batched measurements")
+                    help="skip the time-to-tolerance, batched and straight-duct measurements")
     ap.add_argument("--duct-study", action="store_true",
-                    help="also run the straight-duct self-convergence study (reported in the JSON line)")
+                    help="run the straight-duct study (about a second) also with --no-extras")
     ap.add_argument("--launch-shape", default=None,
                     help="strip_h,corr_block,pg_fused for the timed problem (default: the library's)")
     ap.add_argument("--calibration-copy-mib", type=int, default=0,
@@ -587,7 +587,7 @@ def main():
         line["time_to_tol"] = time_to_tolerance(log)
         torch.cuda.empty_cache()
         line["batched"] = batched(log)
-    if args.duct_study:
+    if args.duct_study or not args.no_extras:
         line["duct_study"] = duct_study(log)
     if not args.no_cpu_baseline:
         log("timing the oracle on the host cores")
