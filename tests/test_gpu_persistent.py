@@ -164,3 +164,24 @@ def test_problems_stay_usable_after_a_batch(persistent):
         fresh.mg_cycle(y)
         assert not np.array_equal(x.cpu().numpy(), psi.cpu().numpy())
         assert np.array_equal(x.cpu().numpy(), y.cpu().numpy())
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_non_finite_residual_ends_the_batch(persistent):
+    """A NaN in one problem's starting flux makes its first residual norm non-finite: both batch
+    forms stop and report CTF_ENONFINITE (the persistent kernel through its device error flag), and
+    the problems stay usable."""
+    ctf = _ctf()
+    ws = _uneven("pn", [16, 24], 3800)
+    probs = [_problem(w, 1) for w in ws]
+    psis = [p.zeros() for p in probs]
+    psis[1][0, 3, 5, 7] = float("nan")
+    with pytest.raises(ctf.CtfError) as e:
+        if persistent:
+            ctf.solve_batch_persistent(probs, psis, 1e-6, 50)
+        else:
+            ctf.solve_batch(probs, psis, 1e-6, 50, 2)
+    assert e.value.code == ctf.CTF_ENONFINITE
+    x = probs[0].zeros()
+    probs[0].mg_cycle(x)
+    assert float(x.abs().max()) > 0.0
