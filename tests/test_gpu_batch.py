@@ -108,6 +108,28 @@ def test_results_do_not_depend_on_launch_shape(disc, precision):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_tall_strips_on_a_ragged_grid(precision):
+    """Strips of 256 rows (the default once a launch fills the chip eight times over) on a grid of
+    592 nodes (two full strips and a ragged one of 80 rows, levels down to 37): PG operator and
+    cycles give the bits of strips of 128 and of 32 rows, fused and two-pass."""
+    import torch
+    ctf = _ctf()
+    op, gp = make_pair(workload(N=592, na=1, G=1), "pg", "vac", precision=precision)
+    psi = torch.as_tensor(random_field(op.shape(), seed=23, lo=0.0, hi=1.0), device="cuda")
+    outs = []
+    for strip_h, block, fused in ((256, 256, 1), (128, 256, 1), (32, 512, 0), (256, 1024, 0)):
+        gp.set_launch_shape(strip_h, block, fused)
+        out = gp.empty()
+        gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+        x = psi.clone()
+        for _ in range(2):
+            gp.mg_cycle(x)
+        outs.append((out.cpu().numpy(), x.cpu().numpy()))
+    for o, x in outs[1:]:
+        assert np.array_equal(o, outs[0][0]) and np.array_equal(x, outs[0][1])
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_wide_sweep_blocks_give_the_same_bits(precision):
     """Sweep blocks of 1024 and of 256 threads on a ragged grid wider than 256 nodes (288): the
     same cycle iterates, bit for bit."""

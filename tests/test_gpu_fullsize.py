@@ -146,3 +146,77 @@ def test_c4_fullsize_upwind_residual_sampled():
     h = w.L / w.N
     ref = upwind_residual(f[:, None, :, :] * d[:, sel, None, None], em, st, qs, h, h, (VACUUM,) * 4)
     assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def _c4_pg_problem():
+    """The learned-correction workload as the benchmark's refinement step runs it: biquadratic
+    ConvFEM + non-linear PG, float32 cycles with float64 refinement, the library's launch shape."""
+    import sys
+    from paper_2301_09991_amd import ctf
+    w = WORKLOADS["c4_learned"]
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=w.N, length=w.L, p=w.p, na=w.na, ngroups=w.G,
+                             scatter_order=ss.shape[0] - 1, discretisation=ctf.CONVFEM_PG,
+                             precision=ctf.FP32_IR)
+    print("c4 PG full size: creating the problem", file=sys.stderr, flush=True)
+    return w, (st, ss, src), ctf.Problem(cfg, st, ss, src)
+
+
+def test_c4_fullsize_pg_residual_sampled():
+    """The benchmark's headline workload at full size (1024 x 1024 nodes, L = 32, p = 2, 512
+    ordinates: 2^29 DOF) in its default launch shape (strips of 256 rows): float64 PG residual of a
+    structured psi on one ordinate of every face, against the oracle."""
+    import sys
+    import torch
+    from oracle.quadrature import quadrature
+    from oracle.transport import emission_from_moments, moments
+    from paper_2301_09991_amd import ctf
+    w, (st, ss, src), gp = _c4_pg_problem()
+    assert gp.launch_shape() == (256, 256, 1)
+    q = quadrature(w.na)
+    nd = len(q["mu"])
+    f, d = _structured(w.G, w.N, nd, seed=43)
+    psi = _device_product(f, d)
+    out = gp.empty()
+    print("c4 PG full size: residual", file=sys.stderr, flush=True)
+    gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+    na2 = w.na * w.na
+    sel = np.array([fc * na2 + (fc * 29 + 5) % na2 for fc in range(8)])
+    got = out[:, torch.as_tensor(sel, device="cuda")].cpu().numpy()
+    del psi, out, gp
+    torch.cuda.empty_cache()
+    Phi = f[:, None, :, :] * moments(d[:, :, None, None], q)
+    qs = _subquad(q, sel)
+    em = emission_from_moments(Phi, qs, ss, src)
+    h = w.L / w.N
+    ref = pg_residual(f[:, None, :, :] * d[:, sel, None, None], em, st, qs, h, h, w.p, (VACUUM,) * 4)
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_c4_fullsize_step_bits_do_not_depend_on_launch_shape():
+    """At full size, the refinement step the benchmark times (strips of 256 rows, fused PG form)
+    gives the bits of the launch shapes that the small-size tests check against the oracle (strips
+    of 128 rows, fused; strips of 32 rows, two-pass form): the float32 PG kernels, the float64
+    residual and update, and the coarse levels, over one step from a structured psi."""
+    import sys
+    import torch
+    w, _, gp = _c4_pg_problem()
+    nd = 8 * w.na * w.na
+    f, d = _structured(w.G, w.N, nd, seed=47)
+    psi0 = _device_product(f, d)
+    ref = None
+    for shape in ((256, 256, 1), (128, 256, 1), (32, 256, 0)):
+        gp.set_launch_shape(*shape)
+        x = psi0.clone()
+        print(f"c4 PG full size: one step, launch shape {shape}", file=sys.stderr, flush=True)
+        rel = gp.mg_cycle(x, want_residual=True)
+        assert np.isfinite(rel)
+        if ref is None:
+            ref = (x, rel)
+            assert not torch.equal(x, psi0)
+        else:
+            assert rel == ref[1]
+            assert torch.equal(x, ref[0])
+            del x
+    del psi0, ref, gp
+    torch.cuda.empty_cache()
