@@ -392,21 +392,23 @@ struct PGArgs {
 // registers, so every input value is read from HBM about once.
 constexpr int kStripW = 64;
 
-// Logical block of a strip kernel (grid: strips x ordinates x groups).  The hardware hands out
-// workgroups round-robin over the 8 XCDs by linear block id; the blocks one XCD receives get a
-// contiguous range of logical ids, so that each XCD streams whole (ordinate, group) planes strip
-// after strip and its own L2 keeps the per-cell data and the rows shared by neighbouring strips.
+// Logical block of a strip kernel (grid: strips x ordinates x groups; strip = strip row * ntx +
+// strip column).  The hardware hands out workgroups round-robin over the 8 XCDs by linear block
+// id; the blocks one XCD receives get a contiguous range of logical ids, taken in the order strip
+// column (fastest), ordinate, strip row, group.  So one XCD runs the strips of one strip row side
+// by side, and its own L2 keeps the psi rows neighbouring strips share, and it goes through the
+// ordinates of that strip row while the row's per-cell planes (emission, sigma_t) stay in its L2.
 constexpr unsigned kXcds = 8;
 struct StripBlock {
   int strip, dir, g;
 };
-__device__ __forceinline__ StripBlock strip_block() {
+__device__ __forceinline__ StripBlock strip_block(unsigned ntx) {
   const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
   const unsigned b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const unsigned x = b % kXcds, k = b / kXcds, q = nb / kXcds, rm = nb % kXcds;
   const unsigned L = x * q + (x < rm ? x : rm) + k;
-  const unsigned pl = L / gridDim.x;
-  return StripBlock{int(L % gridDim.x), int(pl % gridDim.y), int(pl / gridDim.y)};
+  const unsigned r1 = L / ntx, r2 = r1 / gridDim.y, nrow = gridDim.x / ntx;
+  return StripBlock{int((r2 % nrow) * ntx + L % ntx), int(r1 % gridDim.y), int(r2 / nrow)};
 }
 
 template <typename T, int W>
@@ -484,7 +486,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_stream(PGArgs<T> a) {
   __shared__ T s_row[D][3][RW];   // psi, k_x, k_y side by side (one base address per row)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const StripBlock sb = strip_block();
+  const StripBlock sb = strip_block(unsigned(a.ntx));
   const int x0 = (sb.strip % a.ntx) * kStripW, y0 = (sb.strip / a.ntx) * a.strip_h;
   const int dir = sb.dir, g = sb.g;
   const size_t ncell = size_t(n) * n;
@@ -668,7 +670,7 @@ __global__ __launch_bounds__(kStripW) void k_pg_diffusivity(PGArgs<T> a) {
   __shared__ T s_g[D][2][kStripW];   // Psi_x, Psi_y side by side
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const StripBlock sb = strip_block();
+  const StripBlock sb = strip_block(unsigned(a.ntx));
   const int xs = (sb.strip % a.ntx) * OW, y0 = (sb.strip / a.ntx) * a.strip_h;
   const int x0 = xs - P;                 // column of lane 0 (Psi is formed for x0 .. x0 + 63)
   const int dir = sb.dir, g = sb.g;
@@ -875,7 +877,7 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
   __shared__ T s_k[KR][2][GW];   // k_x, k_y (columns outside the domain: the k halo copy)
   const int n = a.L.dims.n;
   const int lane = threadIdx.x;
-  const StripBlock sb = strip_block();
+  const StripBlock sb = strip_block(unsigned(a.ntx));
   const int xs = (sb.strip % a.ntx) * OW, y0 = (sb.strip / a.ntx) * a.strip_h;
   const int c0 = xs - 2 * P;            // column of lane 0
   const int dir = sb.dir, g = sb.g;
