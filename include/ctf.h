@@ -275,8 +275,8 @@ size_t ctf_solve_batch_persistent_bytes(ctf_problem* const* probs, int nprob, in
  * the non-linear PG whether the diffusivities are formed in the residual's own pass (pg_fused = 1)
  * or in a pass of their own whose result the residual pass reads (0).  Results do not depend on
  * the shape.  Defaults: strip_h 128 (256 once a
- * PG launch has at least eight rounds of 4096 wavefront slots), corr_block 256, pg_fused 1 for p <= 3
- * and 0 for p = 4. */
+ * PG launch has at least eight rounds of 4096 wavefront slots, 512 once it has sixteen with
+ * 512-row strips), corr_block 256, pg_fused 1 for p <= 3 and 0 for p = 4. */
 int ctf_set_launch_shape(ctf_problem* prob, int strip_h, int corr_block, int pg_fused);
 int ctf_get_launch_shape(const ctf_problem* prob, int* strip_h, int* corr_block, int* pg_fused);
 

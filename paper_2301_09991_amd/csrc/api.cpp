@@ -872,12 +872,15 @@ int ctf_create_problem(const ctf_config* cfg, const double* sigma_t, const doubl
   P->pg_fused = cfg->p >= 4 ? 0 : 1;
   // strips of 256 rows instead of 128 once the PG launch still has at least eight rounds of the
   // chip's 4096 wavefront slots: fewer halo rows per output row (7p per strip), measured 2% faster
-  // on the 1024^2 x 512 workload; smaller problems keep 128 rows to fill the chip
+  // on the 1024^2 x 512 workload; smaller problems keep 128 rows to fill the chip.  Strips of 512
+  // rows once that launch still has sixteen rounds (the 512^2 x 2048-ordinate x 4-group workload:
+  // step 306 -> 302 ms; on 1024^2 x 512 ordinates, 4.75 rounds, 512 rows were 0.8% slower)
   {
     const long long ow = 64 - 4 * (cfg->p < 1 ? 1 : cfg->p);
-    const long long blocks256 = ((cfg->n + ow - 1) / ow) * ((cfg->n + 255) / 256) *
-                                (cfg->hemisphere ? 4LL : 8LL) * cfg->na * cfg->na * cfg->ngroups;
-    if (blocks256 >= 8LL * 4096) P->strip_h = 256;
+    const long long planes = (cfg->hemisphere ? 4LL : 8LL) * cfg->na * cfg->na * cfg->ngroups;
+    const long long ntx = (cfg->n + ow - 1) / ow;
+    if (ntx * ((cfg->n + 255) / 256) * planes >= 8LL * 4096) P->strip_h = 256;
+    if (ntx * ((cfg->n + 511) / 512) * planes >= 16LL * 4096) P->strip_h = 512;
   }
 
   hipStream_t s = P->stream;

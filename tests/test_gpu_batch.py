@@ -110,14 +110,15 @@ def test_results_do_not_depend_on_launch_shape(disc, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_tall_strips_on_a_ragged_grid(precision):
     """Strips of 256 rows (the default once a launch fills the chip eight times over) on a grid of
-    592 nodes (two full strips and a ragged one of 80 rows, levels down to 37): PG operator and
-    cycles give the bits of strips of 128 and of 32 rows, fused and two-pass."""
+    592 nodes (two full strips and a ragged one of 80 rows, levels down to 37), and of 512 rows (one
+    full strip and a ragged one): PG operator and cycles give the bits of strips of 128 and of 32
+    rows, fused and two-pass."""
     import torch
     ctf = _ctf()
     op, gp = make_pair(workload(N=592, na=1, G=1), "pg", "vac", precision=precision)
     psi = torch.as_tensor(random_field(op.shape(), seed=23, lo=0.0, hi=1.0), device="cuda")
     outs = []
-    for strip_h, block, fused in ((256, 256, 1), (128, 256, 1), (32, 512, 0), (256, 1024, 0)):
+    for strip_h, block, fused in ((256, 256, 1), (128, 256, 1), (32, 512, 0), (256, 1024, 0), (512, 256, 1)):
         gp.set_launch_shape(strip_h, block, fused)
         out = gp.empty()
         gp.apply_operator(psi, out, ctf.OP_RESIDUAL)

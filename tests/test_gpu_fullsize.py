@@ -81,8 +81,8 @@ def _subquad(q, sel):
 
 def test_c2_fullsize_residual_sampled():
     """The largest workload: 512 x 512 nodes, p = 3, 2048 ordinates, 4 groups with P1 scattering,
-    2^31 DOF (offsets past 32 bits).  float64 residual of a structured psi on one ordinate of every
-    face and all groups, against the oracle."""
+    2^31 DOF (offsets past 32 bits), in its default launch shape (one strip of 512 rows).  float64
+    residual of a structured psi on one ordinate of every face and all groups, against the oracle."""
     import sys
     import torch
     from oracle.quadrature import quadrature
@@ -94,6 +94,7 @@ def test_c2_fullsize_residual_sampled():
                              discretisation=ctf.CONVFEM_PG, precision=ctf.FP64)
     print("c2 full size: creating the problem", file=sys.stderr, flush=True)
     gp = ctf.Problem(cfg, st, ss, src)
+    assert gp.launch_shape() == (512, 256, 1)   # the benchmark's launch shape for this workload
     q = quadrature(w.na)
     nd = len(q["mu"])
     f, d = _structured(w.G, w.N, nd, seed=31)
