@@ -281,7 +281,7 @@ int ctf_set_launch_shape(ctf_problem* prob, int strip_h, int corr_block, int pg_
 int ctf_get_launch_shape(const ctf_problem* prob, int* strip_h, int* corr_block, int* pg_fused);
 
 /* Autotuner: time the candidate launch shapes of the finest-level kernels on this problem's own
- * buffers (strip heights 8..256 and fused / two-pass for ConvFEM/PG, sweep blocks 64..1024),
+ * buffers (strip heights 8..512 and fused / two-pass for ConvFEM/PG, sweep blocks 64..1024),
  * keep the fastest, and
  * record them in the JSON file cache_path under a key of (p, discretisation, precision, n, n_dir,
  * groups).  A problem whose key is already cached takes the cached shape without timing unless

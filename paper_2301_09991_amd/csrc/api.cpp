@@ -1512,7 +1512,7 @@ int ctf_autotune(ctf_problem* P, const char* cache_path, int force, int* strip_h
     int best_f = P->pg_fused;
     if (c.discretisation != CTF_UPWIND) {
       for (int fz = 0; fz < (c.discretisation == CTF_CONVFEM_PG ? 2 : 1); ++fz)
-      for (int h : {8, 16, 32, 64, 128, 256}) {
+      for (int h : {8, 16, 32, 64, 128, 256, 512}) {
         P->strip_h = h;
         P->pg_fused = fz;
         double ms = 0.0;

@@ -155,7 +155,7 @@ def test_autotune_picks_and_caches_a_shape():
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "tune.json")
         h, b, f = prob.autotune(path)
-        assert h in (8, 16, 32, 64, 128, 256) and b in (64, 128, 256, 512, 1024) and f in (0, 1)
+        assert h in (8, 16, 32, 64, 128, 256, 512) and b in (64, 128, 256, 512, 1024) and f in (0, 1)
         assert os.path.exists(path)
         text = open(path).read()
         assert '"strip_h": %d' % h in text
