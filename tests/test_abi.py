@@ -56,6 +56,10 @@ def test_config_validation():
         ctf.workspace_bytes(ctf.default_config(n=1))
     with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(n=32770))
+    # planes stay below 2^29 bytes in float64 (the strip kernels address a plane with 32-bit offsets)
+    with pytest.raises(ctf.CtfError):
+        ctf.workspace_bytes(ctf.default_config(n=8194))
+    assert ctf.workspace_bytes(ctf.default_config(n=8192, na=1)) > 8 * 8192 * 8192 * 8
     with pytest.raises(ctf.CtfError):
         ctf.workspace_bytes(ctf.default_config(n_jacobi=0))
     with pytest.raises(ctf.CtfError):
