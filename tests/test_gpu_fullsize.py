@@ -221,3 +221,46 @@ def test_c4_fullsize_step_bits_do_not_depend_on_launch_shape():
             del x
     del psi0, ref, gp
     torch.cuda.empty_cache()
+
+
+def test_largest_grid_pg_residual_on_windows():
+    """The largest grid the library takes (8192 x 8192 nodes, p = 2, one ordinate per face: float64
+    planes of 2^29 bytes, row offsets up to 2^29) in its default launch shape: float64 PG residual
+    of a structured psi against the oracle on three windows (both domain corners and the centre).
+    The oracle runs on each window plus a 16-cell margin on its sides inside the domain; the
+    residual at a cell depends on psi within 3p = 6 cells, so the margin's own boundary does not
+    reach the window."""
+    import sys
+    import torch
+    from oracle.quadrature import quadrature
+    from oracle.transport import emission_from_moments, moments
+    from paper_2301_09991_amd import ctf
+    from workloads import Workload
+    N, WIN, M = 8192, 48, 16
+    w = Workload("largest_grid", N, 1.0, 2, 1, 1, 256, "iso", "gaussian", seed=51)
+    st, ss, src = make_inputs(w)
+    cfg = ctf.default_config(n=N, length=w.L, p=w.p, na=w.na, ngroups=w.G, scatter_order=0,
+                             discretisation=ctf.CONVFEM_PG, precision=ctf.FP64)
+    print("largest grid: creating the problem", file=sys.stderr, flush=True)
+    gp = ctf.Problem(cfg, st, ss, src)
+    assert gp.launch_shape()[0] == 256
+    q = quadrature(w.na)
+    f, d = _structured(w.G, N, len(q["mu"]), seed=53)
+    psi = _device_product(f, d)
+    out = gp.empty()
+    print("largest grid: residual", file=sys.stderr, flush=True)
+    gp.apply_operator(psi, out, ctf.OP_RESIDUAL)
+    windows = [(0, 0), (N // 2 - WIN // 2, N // 3), (N - WIN, N - WIN)]
+    got = [out[:, :, j0:j0 + WIN, i0:i0 + WIN].cpu().numpy() for j0, i0 in windows]
+    del psi, out, gp
+    torch.cuda.empty_cache()
+    md = moments(d[:, :, None, None], q)
+    h = w.L / N
+    for (j0, i0), g in zip(windows, got):
+        a0, a1 = max(j0 - M, 0), min(j0 + WIN + M, N)
+        b0, b1 = max(i0 - M, 0), min(i0 + WIN + M, N)
+        fc = f[:, a0:a1, b0:b1]
+        em = emission_from_moments(fc[:, None] * md, q, ss[..., a0:a1, b0:b1], src[:, a0:a1, b0:b1])
+        ref = pg_residual(fc[:, None] * d[:, :, None, None], em, st[:, a0:a1, b0:b1], q, h, h, w.p,
+                          (VACUUM,) * 4)[:, :, j0 - a0:j0 - a0 + WIN, i0 - b0:i0 - b0 + WIN]
+        assert np.abs(g - ref).max() <= 1e-12 * np.abs(ref).max(), (j0, i0)
