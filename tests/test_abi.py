@@ -84,3 +84,28 @@ def test_default_config_is_the_papers():
     c = ctf.default_config()
     assert c.beta_pg == 3.0 and c.alpha_r == 3.0 and c.eps_k == 1e-3
     assert c.n_jacobi == 2 and c.bc[:] == [ctf.VACUUM] * 4
+
+
+def test_null_and_empty_arguments_are_refused():
+    """Every entry point checks its arguments before it touches a device: null handles and
+    buffers, empty batches and negative counts return CTF_EINVAL with a message."""
+    lib = ctf.load()
+    null = ctypes.c_void_p(0)
+    info = ctf.SolveInfo()
+    one = (ctypes.c_void_p * 1)(0)
+    calls = [
+        lambda: lib.ctf_apply_operator(null, null, null, ctf.OP_RESIDUAL),
+        lambda: lib.ctf_mg_cycle(null, null, None),
+        lambda: lib.ctf_solve(null, null, 1e-6, 10, ctypes.byref(info)),
+        lambda: lib.ctf_smooth(null, 0, 0, null, null, 1),
+        lambda: lib.ctf_moments(null, null, null),
+        lambda: lib.ctf_restrict(null, 0, null, null),
+        lambda: lib.ctf_solve_batch(one, 0, one, 1e-6, 10, 1, None),
+        lambda: lib.ctf_solve_batch(None, 1, one, 1e-6, 10, 1, None),
+        lambda: lib.ctf_solve_batch_persistent(one, 0, one, 1e-6, 10, 0, null, 0, None),
+        lambda: lib.ctf_set_launch_shape(null, 128, 256, 1),
+    ]
+    for call in calls:
+        assert call() == ctf.CTF_EINVAL
+        assert lib.ctf_last_error().decode()
+    assert lib.ctf_solve_batch_persistent_bytes(one, 0, 0) == 0
