@@ -185,3 +185,16 @@ def test_non_finite_residual_ends_the_batch(persistent):
     x = probs[0].zeros()
     probs[0].mg_cycle(x)
     assert float(x.abs().max()) > 0.0
+
+
+@pytest.mark.parametrize("rtol", [1e-6, 2.0])
+def test_single_problem_and_immediate_convergence(rtol):
+    """A batch of one problem, and a tolerance the starting flux already meets (rtol = 2 with
+    psi = 0, whose relative residual is 1): both forms agree bit for bit, the latter after the one
+    step that evaluates the first residual."""
+    ws = _uneven("ps", [20], 3900)
+    a, b = _both(ws, 1, 200, rtol=rtol)
+    assert a[0] and b[0]
+    _same(a, b)
+    if rtol > 1:
+        assert b[1][0]["outer_steps"] <= 1
