@@ -1210,13 +1210,16 @@ __global__ __launch_bounds__(kStripW, P == 2 ? (sizeof(T) == 4 ? (ACC ? 3 : 4) :
 // finest upwind operator (eq. discretised_hfm): rho = q - A_up psi - sigma_t psi
 // mode 0: out = sign * rho (to out and / or out_f), with one float64 partial sum of
 // w_n h^2 (sign rho)^2 per block when partial is given; mode 1: out = psi + rho / d (a Jacobi sweep).
-// Threads are laid out as in the correction sweep below: 64 columns x row groups of kCorrRows rows,
+// Threads are laid out as in the correction sweep below: 64 columns x row groups of R rows,
 // each thread walking its rows in the ordinate's downwind y order with every load issued up front
 // from clamped addresses, so psi is read once for the centre and once, from cache, as x neighbour.
 // A block takes K consecutive ordinates of one face (same signs, so the same walk and upwind
 // column): the per-cell emission and sigma_t of its rows are loaded once for all K.
 constexpr int kCorrRows = 8;
 constexpr int kFullBlock = 256;
+// rows per thread of the finest upwind operator: fewer in float64, whose values take two
+// registers (eight rows held 212 registers per thread with four ordinates per block: two waves)
+template <typename T> constexpr int full_rows() { return sizeof(T) == 8 ? 4 : 8; }
 template <typename T, int K>
 __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, int bc_vac,
                                                             const T* __restrict__ psi,
@@ -1225,18 +1228,19 @@ __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, in
                                                             int mode, T sign, const T* __restrict__ rhs,
                                                             double* __restrict__ partial) {
   if (idle(L.dims.active)) return;
+  constexpr int R = full_rows<T>();
   const int n = L.dims.n, nd = L.dims.nd;
   const int ntx = (n + 63) >> 6;
   const int tx = int(vb.x) % ntx, ty = int(vb.x) / ntx;
   const int i = tx * 64 + int(threadIdx.x & 63);
-  const int jb = (ty * (kFullBlock / 64) + int(threadIdx.x >> 6)) * kCorrRows;
+  const int jb = (ty * (kFullBlock / 64) + int(threadIdx.x >> 6)) * R;
   const int d0 = int(vb.y) * K, g = vb.z;
   const size_t ncell = size_t(n) * n;
   double acc = 0.0;   // sum over the block's ordinates of w_n (sign rho)^2
   if (i < n && jb < n) {
     const T h = T(L.dims.h);
     const T mu0 = L.mu[d0], nu0 = L.nu[d0];   // signs shared by the K ordinates
-    const int je = min(jb + kCorrRows, n);
+    const int je = min(jb + R, n);
     const int iu = mu0 > T(0) ? i - 1 : i + 1;
     const bool x_in = iu >= 0 && iu < n;
     const int iuc = clampi(iu, 0, n - 1);
@@ -1250,9 +1254,9 @@ __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, in
     const bool y_in = ju >= 0 && ju < n;
     const int rows = je - jb;
     // per-cell values, once for the K ordinates
-    T q0[kCorrRows], q1[kCorrRows], q2[kCorrRows], vs[kCorrRows];
+    T q0[R], q1[R], q2[R], vs[R];
 #pragma unroll
-    for (int t = 0; t < kCorrRows; ++t) {
+    for (int t = 0; t < R; ++t) {
       const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
       const size_t row = size_t(j) * n;
       q0[t] = E0[row + i];
@@ -1261,7 +1265,7 @@ __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, in
     }
     if (nmomE > 1) {
 #pragma unroll
-      for (int t = 0; t < kCorrRows; ++t) {
+      for (int t = 0; t < R; ++t) {
         const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
         const size_t row = size_t(j) * n;
         q1[t] = E0[ncell + row + i];
@@ -1276,9 +1280,9 @@ __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, in
       const T amu = tabs(mu) / h, anu = tabs(nu) / h;
       const T* __restrict__ pp = psi + plane;
       const T* __restrict__ rp = rhs ? rhs + plane : pp;
-      T vc[kCorrRows], vx[kCorrRows], vr[kCorrRows];
+      T vc[R], vx[R], vr[R];
 #pragma unroll
-      for (int t = 0; t < kCorrRows; ++t) {
+      for (int t = 0; t < R; ++t) {
         const int j = down ? min(j0 + t, je - 1) : max(j0 - t, jb);
         const size_t row = size_t(j) * n;
         vc[t] = pp[row + i];
@@ -1288,7 +1292,7 @@ __device__ __forceinline__ void b_upwind_full(const VBlk& vb, LevelData<T> L, in
       T prev = pp[size_t(clampi(ju, 0, n - 1)) * n + i];   // the upwind row, used only inside the domain
       double acck = 0.0;
 #pragma unroll
-      for (int t = 0; t < kCorrRows; ++t) {
+      for (int t = 0; t < R; ++t) {
         if (t >= rows) break;
         const size_t cell = size_t(down ? j0 + t : j0 - t) * n + i;
         const T pc = vc[t];
@@ -1997,8 +2001,8 @@ size_t pg_partials(const LevelDims& d, int strip_h) {
   return strips * d.nd * d.G;
 }
 
-size_t upwind_full_blocks(const LevelDims& d) {
-  const int rows_per_block = (kFullBlock / 64) * kCorrRows;
+size_t upwind_full_blocks(const LevelDims& d) {   // the larger count of the two precisions
+  const int rows_per_block = (kFullBlock / 64) * full_rows<double>();
   return size_t((d.n + 63) / 64) * ((d.n + rows_per_block - 1) / rows_per_block) * d.nd * d.G;
 }
 
@@ -2007,7 +2011,7 @@ hipError_t launch_upwind_full(const LevelData<T>& L, int bc_vac, const T* psi, c
                               T* out, int mode, T sign, const T* rhs, hipStream_t s, float* out_f,
                               double* partial, size_t partial_cap, int* npartial) {
   const int n = L.dims.n;
-  const int rows_per_block = (kFullBlock / 64) * kCorrRows;
+  const int rows_per_block = (kFullBlock / 64) * full_rows<T>();
   // ordinates per block: four when a face holds a multiple of four (n_dir = 8 or 4 faces of na^2)
   const int per_face = L.dims.na * L.dims.na;
   const int kb = per_face % 4 == 0 ? 4 : 1;
