@@ -107,15 +107,16 @@ def test_results_do_not_depend_on_launch_shape(disc, precision):
         assert np.array_equal(o, outs[0][0]) and np.array_equal(x, outs[0][1])
 
 
-@pytest.mark.parametrize("precision", [0, 1])
-def test_tall_strips_on_a_ragged_grid(precision):
+@pytest.mark.parametrize("precision,p,scatter,G", [(0, 2, "iso", 1), (1, 2, "iso", 1), (2, 3, "p1", 2)])
+def test_tall_strips_on_a_ragged_grid(precision, p, scatter, G):
     """Strips of 256 rows (the default once a launch fills the chip eight times over) on a grid of
     592 nodes (two full strips and a ragged one of 80 rows, levels down to 37), and of 512 rows (one
     full strip and a ragged one): PG operator and cycles give the bits of strips of 128 and of 32
-    rows, fused and two-pass."""
+    rows, fused and two-pass.  Also at p = 3 with P1 scattering over two groups and the bf16 MFMA
+    moments (the largest workload's recipe)."""
     import torch
     ctf = _ctf()
-    op, gp = make_pair(workload(N=592, na=1, G=1), "pg", "vac", precision=precision)
+    op, gp = make_pair(workload(N=592, na=1, G=G, scatter=scatter, p=p), "pg", "vac", precision=precision)
     psi = torch.as_tensor(random_field(op.shape(), seed=23, lo=0.0, hi=1.0), device="cuda")
     outs = []
     for strip_h, block, fused in ((256, 256, 1), (128, 256, 1), (32, 512, 0), (256, 1024, 0), (512, 256, 1)):
