@@ -163,3 +163,19 @@ def test_autotune_picks_and_caches_a_shape():
         other = _problem(w, ctf.FP32_IR, disc=ctf.CONVFEM_PG)
         assert other.autotune(path) == (h, b, f)
         assert other.launch_shape() == (h, b, f)
+
+
+def test_launch_shape_limits():
+    """Strip heights 8..512, sweep blocks that are multiples of 64 up to 1024 and pg_fused 0/1 are
+    accepted; anything else is refused with CTF_EINVAL and leaves the shape as it was."""
+    ctf = _ctf()
+    w = Workload("shape", 32, 1.0, 2, 1, 1, 4, "iso", "box_quarter", seed=5)
+    prob = _problem(w, ctf.FP64, disc=ctf.CONVFEM_PG)
+    prob.set_launch_shape(512, 1024, 0)
+    assert prob.launch_shape() == (512, 1024, 0)
+    prob.set_launch_shape(8, 64, 1)
+    for bad in ((7, 256, 1), (513, 256, 1), (128, 96, 1), (128, 1088, 1), (128, 0, 1), (128, 256, 2)):
+        with pytest.raises(ctf.CtfError) as e:
+            prob.set_launch_shape(*bad)
+        assert e.value.code == ctf.CTF_EINVAL
+        assert prob.launch_shape() == (8, 64, 1)

@@ -198,3 +198,20 @@ def test_single_problem_and_immediate_convergence(rtol):
     _same(a, b)
     if rtol > 1:
         assert b[1][0]["outer_steps"] <= 1
+
+
+@pytest.mark.parametrize("persistent", [False, True])
+def test_a_problem_twice_in_a_batch_is_refused(persistent):
+    """The same problem twice in one batch (its steps would race on one set of buffers) is refused
+    with CTF_EINVAL before anything runs."""
+    ctf = _ctf()
+    w = _uneven("pd", [16], 4000)[0]
+    prob = _problem(w, 1)
+    psis = [prob.zeros(), prob.zeros()]
+    with pytest.raises(ctf.CtfError) as e:
+        if persistent:
+            ctf.solve_batch_persistent([prob, prob], psis, 1e-6, 10)
+        else:
+            ctf.solve_batch([prob, prob], psis, 1e-6, 10, 1)
+    assert e.value.code == ctf.CTF_EINVAL
+    assert all(float(x.abs().max()) == 0.0 for x in psis)
